@@ -1,0 +1,195 @@
+/*
+ * fcmp.h -- fast correlation for matching pursuit on AMD MI355X (gfx950).
+ *
+ * C ABI of libfcmp.so.  The library recovers a K-sparse x from
+ * y = Phi x + eta, Phi = S_Omega U (eq. (CSbasic); Sec. I defines S_Omega as
+ * the M rows, indexed by Omega, of the N x N identity), for the two unitary
+ * classes the paper names: the unitary DFT and the Sylvester-ordered
+ * Hadamard matrix.  The hot step of every matching pursuit algorithm is the
+ * correlation h = Phi^H r (Algorithm 1.1, step 2); the library computes it
+ * either as one N-point transform of the zero-filled residual ("conventional",
+ * Sec. III-B) or by the paper's method, h = h_0 - sum_tau x(tau) P_lambda c
+ * (eqs. (kernelsum), (kernelsumOMP)), with the identification argmax fused
+ * into the kernel that produces h.  Least squares is an FP64 incremental
+ * inverse-Cholesky update on the selected columns (Algorithm 1.1, step 6).
+ *
+ * Conventions (0-based, N a power of two):
+ *   Fourier : U[k][n] = exp(-2 pi i ((k n) mod N) / N) / sqrt(N)
+ *   Hadamard: U[k][n] = (-1)^popcount(k & n) / sqrt(N)
+ *   Identification picks argmax |h(j)|^2 over columns not yet selected; ties
+ *   go to the lowest index.
+ *
+ * Data types on the device:
+ *   Hadamard vectors (y, x, h) are float64; Fourier vectors are complex128
+ *   stored as interleaved (re, im) float64 pairs.  "Correlation precision"
+ *   FP32 means the correlation runs in float32 / complex64 while h_0, the
+ *   kernel-vector Gram entries and all least squares stay FP64.
+ *
+ * Memory ownership: the caller owns every device buffer.  The library never
+ * allocates device memory: each call that needs scratch space takes a device
+ * workspace whose size the matching *_query_workspace call returns (host-only,
+ * no HIP call).  Host arrays passed in (Omega) are read before the call
+ * returns.  Opaque handles (plans, servers) are host objects freed by their
+ * *_destroy call.
+ *
+ * Streams: device work is enqueued on the caller's hipStream_t (passed as
+ * void*; NULL = the null stream).  Outputs are valid once that stream has
+ * been synchronised.  Calls that take a host stats pointer synchronise the
+ * stream before returning when that pointer is non-NULL.
+ *
+ * Errors: every call returns FCMP_OK (0) or a negative status.  Validation is
+ * host-only and precedes any device work, so an FCMP_E_INVALID or
+ * FCMP_E_WORKSPACE return leaves all outputs untouched.  fcmp_last_error()
+ * returns a thread-local description of the most recent failure.
+ */
+#ifndef FCMP_H
+#define FCMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCMP_ABI_VERSION 1
+
+/* status codes */
+#define FCMP_OK            0
+#define FCMP_E_INVALID    -1   /* bad argument (sizes, Omega, enums, pointers) */
+#define FCMP_E_WORKSPACE  -2   /* workspace smaller than the query returned */
+#define FCMP_E_DEVICE     -3   /* a HIP runtime error; see fcmp_last_error() */
+#define FCMP_E_BUSY       -4   /* server queue full */
+#define FCMP_E_NUMERIC    -5   /* Cholesky breakdown (Gram not positive) */
+#define FCMP_E_NOTFOUND   -6   /* unknown ticket */
+
+/* matrix classes (Sec. I: partial Hadamard, partial Fourier) */
+#define FCMP_HADAMARD 0
+#define FCMP_FOURIER  1
+
+/* algorithms: OMP is Algorithm 1.1; SP and CoSaMP are the cited MPAs */
+#define FCMP_OMP    0
+#define FCMP_SP     1
+#define FCMP_COSAMP 2
+
+/* correlation methods */
+#define FCMP_CORR_CONVENTIONAL 0  /* N-point transform of the zero-filled residual */
+#define FCMP_CORR_FAST         1  /* eq. (kernelsumOMP): h_0 - sum x P c          */
+#define FCMP_CORR_ADAPTIVE     2  /* fast up to a switch iteration, then conventional
+                                     (the adaptive strategy of Sec. IV)           */
+
+/* correlation precision (least squares is always FP64) */
+#define FCMP_FP64 0
+#define FCMP_FP32 1
+
+/* Problem statement, eq. (CSbasic): Phi = S_Omega U with |Omega| = M.
+ * N: power of two in [2, 2^24] (Fourier: [2, 2^22]); M in [1, N]; K in [1, M-1] (K < M, Sec. I).
+ * omega: HOST pointer, M strictly increasing indices in [0, N).            */
+typedef struct {
+  int32_t matrix_class;      /* FCMP_HADAMARD or FCMP_FOURIER */
+  int32_t reserved;
+  int64_t N, M, K;
+  const int32_t* omega;
+} fcmp_problem;
+
+typedef struct {
+  int32_t algorithm;         /* FCMP_OMP / FCMP_SP / FCMP_COSAMP */
+  int32_t corr_method;       /* FCMP_CORR_* */
+  int32_t corr_precision;    /* FCMP_FP64 / FCMP_FP32 */
+  int32_t max_iter;          /* SP/CoSaMP outer iterations (0 = 50); OMP runs K */
+  int32_t switch_t;          /* ADAPTIVE: last iteration that uses the fast method
+                                (0 = library's tuned value) */
+  int32_t reserved;
+  double  res_tol;           /* reserved, must be 0 */
+} fcmp_options;
+
+typedef struct {
+  int32_t iterations;        /* OMP: selections made; SP/CoSaMP: outer iterations */
+  int32_t status;            /* FCMP_OK or FCMP_E_NUMERIC */
+  double  res_norm;          /* ||y - Phi_Lambda x|| (from the normal equations) */
+  double  ms_total;          /* device time of the solve (hipEvent), ms */
+} fcmp_stats;
+
+int         fcmp_abi_version(void);
+const char* fcmp_status_str(int status);
+const char* fcmp_last_error(void);
+
+/* ---- whole solves ---------------------------------------------------- */
+
+/* Device bytes fcmp_solve needs for this problem and options.  Host-only. */
+int fcmp_query_workspace(const fcmp_problem* prob, const fcmp_options* opt,
+                         size_t* bytes);
+
+/* Recover x from y (Algorithm 1.1 for OMP).
+ * y_dev      : device, M values (float64 | complex128)
+ * ws_dev     : device workspace of ws_bytes >= fcmp_query_workspace()
+ * support_dev: device int32[K]; OMP: selection order; SP/CoSaMP: ascending;
+ *              entries past the last selection are -1
+ * x_dev      : device, K values (float64 | complex128) aligned with support
+ * stats      : host, nullable; when given the call synchronises the stream  */
+int fcmp_solve(const fcmp_problem* prob, const fcmp_options* opt,
+               const void* y_dev, void* ws_dev, size_t ws_bytes,
+               int32_t* support_dev, void* x_dev, fcmp_stats* stats,
+               void* hip_stream);
+
+/* Many independent problems in one call.  Problems of one shape run in
+ * lockstep; problems small enough for one workgroup's LDS run whole solves
+ * per workgroup in one persistent launch.  Arrays are HOST arrays of n
+ * entries holding device pointers; stats (nullable) is a host array of n. */
+int fcmp_batch_query_workspace(int64_t n, const fcmp_problem* probs,
+                               const fcmp_options* opt, size_t* bytes);
+int fcmp_batch_solve(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
+                     const void* const* y_dev, void* ws_dev, size_t ws_bytes,
+                     int32_t* const* support_dev, void* const* x_dev,
+                     fcmp_stats* stats, void* hip_stream);
+
+/* ---- single steps of the hot path (each one launch sequence) ---------- */
+
+/* Kernel vector c = U^H S_Omega^T S_Omega U e_0 (definition after eq.
+ * (kernelsum)).  c64_dev: N FP64 values (float64 | complex128); cp_dev
+ * (nullable): N values in the correlation precision (float32 | complex64
+ * for FCMP_FP32, else float64 | complex128). */
+int fcmp_kernel_vector_workspace(const fcmp_problem* prob, size_t* bytes);
+int fcmp_kernel_vector(const fcmp_problem* prob, int32_t precision,
+                       void* c64_dev, void* cp_dev, void* ws_dev, size_t ws_bytes,
+                       void* hip_stream);
+
+/* Conventional correlation h = Phi^H r = U^H S_Omega^T r (Algorithm 1.1
+ * step 2) with the identification of step 3 fused.
+ * r_dev  : device, M values in the given precision (float64 | complex128 for
+ *          FP64; float32 | complex64 for FP32), aligned with omega
+ * h_dev  : device (nullable), N values in the same precision
+ * excl_dev: device (nullable), uint32[(N+31)/32] bitmap of excluded columns
+ * sel_dev: device (nullable), 16 bytes {double |h|^2, int64 index} of the winner
+ *          (index -1 when every column is excluded or h vanishes)          */
+int fcmp_correlate_workspace(const fcmp_problem* prob, int32_t precision,
+                             size_t* bytes);
+int fcmp_correlate(const fcmp_problem* prob, int32_t precision,
+                   const void* r_dev, void* h_dev, const uint32_t* excl_dev,
+                   void* sel_dev, void* ws_dev, size_t ws_bytes, void* hip_stream);
+
+/* Fast correlation, eq. (kernelsum): h = h0 - sum_tau x(tau) P_{lam(tau)} c,
+ * with P_lambda the cyclic shift (Fourier) or XOR (Hadamard) permutation of
+ * Thm 2-1 / Sec. III-B, and the identification fused.
+ * h0_dev : N FP64 values; cp_dev: N values in the precision (FP32 or FP64);
+ * lam_dev: int32[ntaps]; xt_dev: ntaps FP64 values; accumulation is FP64.
+ * h_dev, excl_dev, sel_dev as for fcmp_correlate (h_dev is FP64 here).    */
+int fcmp_fast_correlate_workspace(const fcmp_problem* prob, size_t* bytes);
+int fcmp_fast_correlate(const fcmp_problem* prob, int32_t precision,
+                        const void* h0_dev, const void* cp_dev,
+                        const int32_t* lam_dev, const void* xt_dev, int64_t ntaps,
+                        void* h_dev, const uint32_t* excl_dev, void* sel_dev,
+                        void* ws_dev, size_t ws_bytes, void* hip_stream);
+
+/* Forward operator y = Phi x (+ noise scaled to snr_db when noise_dev is not
+ * NULL: eta = g ||Phi x|| / ||g|| 10^(-snr/20)).  x_dev: N FP64 values;
+ * noise_dev: M values; y_dev: M values (float64 | complex128).             */
+int fcmp_measure_workspace(const fcmp_problem* prob, size_t* bytes);
+int fcmp_measure(const fcmp_problem* prob, const void* x_dev, const void* noise_dev,
+                 double snr_db, void* y_dev, void* ws_dev, size_t ws_bytes,
+                 void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCMP_H */

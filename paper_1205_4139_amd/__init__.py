@@ -1,0 +1,247 @@
+"""Python binding of libfcmp.so (fast correlation for matching pursuit on MI355X).
+
+Argument marshalling only: every step of the recovery runs in the library's
+HIP kernels.  Device buffers are torch tensors on the current HIP device;
+work is enqueued on ``torch.cuda.current_stream()``.  There is no CPU
+fallback: importing the binding fails when the library has not been built
+(``python -m paper_1205_4139_amd.build``).
+
+Value types on the device:
+  Hadamard class: float64 (y, x, h_0, kernel vector), float32 in FP32 mode;
+  Fourier class : complex128, complex64 in FP32 mode.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfcmp.so")
+
+HADAMARD, FOURIER = 0, 1
+OMP, SP, COSAMP = 0, 1, 2
+CONVENTIONAL, FAST, ADAPTIVE = 0, 1, 2
+FP64, FP32 = 0, 1
+
+E_OK, E_INVALID, E_WORKSPACE, E_DEVICE, E_BUSY, E_NUMERIC, E_NOTFOUND = 0, -1, -2, -3, -4, -5, -6
+
+CLASS = {"H": HADAMARD, "F": FOURIER, HADAMARD: HADAMARD, FOURIER: FOURIER}
+METHOD = {"conventional": CONVENTIONAL, "fast": FAST, "adaptive": ADAPTIVE}
+ALGO = {"omp": OMP, "sp": SP, "cosamp": COSAMP}
+PREC = {"fp64": FP64, "fp32": FP32}
+
+
+class FcmpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fcmp error {code}: {msg}")
+        self.code = code
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("matrix_class", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("N", ctypes.c_int64), ("M", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("omega", ctypes.POINTER(ctypes.c_int32))]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("algorithm", ctypes.c_int32), ("corr_method", ctypes.c_int32),
+                ("corr_precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("switch_t", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("res_tol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("res_norm", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run: python -m paper_1205_4139_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32, i64, dbl = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P, O = ctypes.POINTER(Problem), ctypes.POINTER(Options)
+    sigs = {
+        "fcmp_abi_version": ([], ctypes.c_int),
+        "fcmp_status_str": ([ctypes.c_int], ctypes.c_char_p),
+        "fcmp_last_error": ([], ctypes.c_char_p),
+        "fcmp_query_workspace": ([P, O, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_solve": ([P, O, vp, vp, sz, vp, vp, ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "fcmp_batch_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_batch_solve": ([i64, P, O, ctypes.POINTER(vp), vp, sz, ctypes.POINTER(vp),
+                              ctypes.POINTER(vp), ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "fcmp_kernel_vector_workspace": ([P, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_kernel_vector": ([P, i32, vp, vp, vp, sz, vp], ctypes.c_int),
+        "fcmp_correlate_workspace": ([P, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_correlate": ([P, i32, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "fcmp_fast_correlate_workspace": ([P, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_fast_correlate": ([P, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "fcmp_measure_workspace": ([P, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_measure": ([P, vp, vp, dbl, vp, vp, sz, vp], ctypes.c_int),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise FcmpError(rc, lib.fcmp_last_error().decode())
+    return rc
+
+
+def make_problem(cls, N: int, M: int, K: int, omega) -> tuple:
+    """(Problem struct, keep-alive omega array)."""
+    om = np.ascontiguousarray(np.asarray(omega, dtype=np.int32))
+    p = Problem(CLASS[cls], 0, int(N), int(M), int(K),
+                om.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return p, om
+
+
+def make_options(algorithm="omp", method="conventional", precision="fp64",
+                 max_iter=0, switch_t=0) -> Options:
+    return Options(ALGO.get(algorithm, algorithm), METHOD.get(method, method),
+                   PREC.get(precision, precision), int(max_iter), int(switch_t), 0, 0.0)
+
+
+# ---------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _dtype(cls, precision="fp64"):
+    torch = _torch()
+    f = CLASS[cls] == FOURIER
+    if PREC.get(precision, precision) == FP32:
+        return torch.complex64 if f else torch.float32
+    return torch.complex128 if f else torch.float64
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class SolveResult:
+    support: "object"      # int32 tensor [K]
+    x: "object"            # float64 / complex128 tensor [K]
+    stats: Optional[Stats]
+
+
+def query_workspace(cls, N, M, K, omega, algorithm="omp", method="conventional",
+                    precision="fp64", switch_t=0) -> int:
+    p, _om = make_problem(cls, N, M, K, omega)
+    o = make_options(algorithm, method, precision, switch_t=switch_t)
+    n = ctypes.c_size_t(0)
+    _check(lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)))
+    return n.value
+
+
+def solve(cls, N, M, K, omega, y, algorithm="omp", method="conventional", precision="fp64",
+          switch_t=0, max_iter=0, stats=True, workspace=None) -> SolveResult:
+    torch = _torch()
+    p, _om = make_problem(cls, N, M, K, omega)
+    o = make_options(algorithm, method, precision, max_iter, switch_t)
+    n = ctypes.c_size_t(0)
+    _check(lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)))
+    dev = y.device
+    ws = workspace if workspace is not None and workspace.numel() >= n.value else _workspace(n.value, dev)
+    sup = torch.empty(int(K), dtype=torch.int32, device=dev)
+    x = torch.empty(int(K), dtype=_dtype(cls), device=dev)
+    st = Stats() if stats else None
+    _check(lib.fcmp_solve(ctypes.byref(p), ctypes.byref(o), _ptr(y), _ptr(ws), ws.numel(),
+                          _ptr(sup), _ptr(x), ctypes.byref(st) if st is not None else None,
+                          _stream()))
+    return SolveResult(sup, x, st)
+
+
+def kernel_vector(cls, N, omega, precision="fp64", device="cuda"):
+    torch = _torch()
+    p, _om = make_problem(cls, N, len(omega), 1, omega)
+    n = ctypes.c_size_t(0)
+    _check(lib.fcmp_kernel_vector_workspace(ctypes.byref(p), ctypes.byref(n)))
+    ws = _workspace(n.value, device)
+    c64 = torch.empty(int(N), dtype=_dtype(cls), device=device)
+    cp = torch.empty(int(N), dtype=_dtype(cls, precision), device=device)
+    _check(lib.fcmp_kernel_vector(ctypes.byref(p), PREC[precision], _ptr(c64), _ptr(cp),
+                                  _ptr(ws), ws.numel(), _stream()))
+    return c64, cp
+
+
+def _sel_tensor(device):
+    torch = _torch()
+    return torch.zeros(2, dtype=torch.float64, device=device)
+
+
+def decode_sel(sel) -> tuple:
+    """(index, |h|^2) from the 16-byte selection record."""
+    a = sel.detach().cpu().numpy()
+    key = float(a[0])
+    idx = int(a[1:2].view(np.int64)[0])
+    return idx, key
+
+
+def correlate(cls, N, omega, r, precision="fp64", excl=None, want_h=True):
+    """h = Phi^H r (conventional, one transform) and the fused selection."""
+    torch = _torch()
+    p, _om = make_problem(cls, N, len(omega), 1, omega)
+    pr = PREC[precision]
+    n = ctypes.c_size_t(0)
+    _check(lib.fcmp_correlate_workspace(ctypes.byref(p), pr, ctypes.byref(n)))
+    ws = _workspace(n.value, r.device)
+    h = torch.empty(int(N), dtype=_dtype(cls, precision), device=r.device) if want_h else None
+    sel = _sel_tensor(r.device)
+    _check(lib.fcmp_correlate(ctypes.byref(p), pr, _ptr(r), _ptr(h), _ptr(excl), _ptr(sel),
+                              _ptr(ws), ws.numel(), _stream()))
+    return h, sel
+
+
+def fast_correlate(cls, N, h0, cp, lam, xt, precision="fp64", excl=None, want_h=True):
+    """h = h0 - sum x P_lam c (eq. (kernelsum)) and the fused selection."""
+    torch = _torch()
+    p, _om = make_problem(cls, N, 1, 1, [0])
+    n = ctypes.c_size_t(0)
+    _check(lib.fcmp_fast_correlate_workspace(ctypes.byref(p), ctypes.byref(n)))
+    ws = _workspace(n.value, h0.device)
+    h = torch.empty(int(N), dtype=_dtype(cls), device=h0.device) if want_h else None
+    sel = _sel_tensor(h0.device)
+    nt = 0 if lam is None else int(lam.numel())
+    _check(lib.fcmp_fast_correlate(ctypes.byref(p), PREC[precision], _ptr(h0), _ptr(cp),
+                                   _ptr(lam), _ptr(xt), nt, _ptr(h), _ptr(excl), _ptr(sel),
+                                   _ptr(ws), ws.numel(), _stream()))
+    return h, sel
+
+
+def measure(cls, N, omega, x, noise=None, snr_db=None):
+    """y = Phi x (+ noise scaled to snr_db)."""
+    torch = _torch()
+    p, _om = make_problem(cls, N, len(omega), 1, omega)
+    n = ctypes.c_size_t(0)
+    _check(lib.fcmp_measure_workspace(ctypes.byref(p), ctypes.byref(n)))
+    ws = _workspace(n.value, x.device)
+    y = torch.empty(len(omega), dtype=_dtype(cls), device=x.device)
+    use_noise = noise is not None and snr_db is not None
+    _check(lib.fcmp_measure(ctypes.byref(p), _ptr(x), _ptr(noise) if use_noise else None,
+                            float(snr_db) if use_noise else 0.0, _ptr(y), _ptr(ws), ws.numel(),
+                            _stream()))
+    return y

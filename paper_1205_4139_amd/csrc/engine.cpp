@@ -1,0 +1,200 @@
+// Host engine: geometry, tables, transform sequencing and validation.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace fcmp {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+const char* last_error() { return g_last_error.c_str(); }
+
+static int ilog2(int64_t n) {
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l;
+}
+
+bool single_ok(int vk, int N) { return (size_t)N * vbytes(vk) <= 131072; }
+
+Geo make_geo(bool fourier, int N) {
+  Geo g;
+  g.N = N;
+  g.fourier = fourier;
+  g.logN = ilog2(N);
+  g.twS = g.logN / 2;
+  g.n2 = g.logN / 2;
+  g.n1 = g.logN - g.n2;
+  const int tile = 4096;
+  g.B1 = std::min(1 << g.n1, std::max(1, tile >> g.n2));
+  g.B2 = std::min(1 << g.n2, std::max(1, tile >> g.n1));
+  g.grouped = !single_ok(fourier ? V_C128 : V_F64, N);
+  g.ngroups = g.grouped ? (1 << g.n1) / g.B1 : 1;
+  return g;
+}
+
+int transform_partials(int vk, const Geo& g) {
+  if (single_ok(vk, g.N)) return 1;
+  return (1 << g.n2) / g.B2;
+}
+
+void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
+  t.ent_k.resize(M);
+  t.perm.resize(M);
+  if (!g.grouped) {
+    for (int m = 0; m < M; ++m) { t.ent_k[m] = omega[m]; t.perm[m] = m; }
+    t.goff.assign(2, 0);
+    t.goff[1] = M;
+  } else {
+    const int mask1 = (1 << g.n1) - 1;
+    const int logB1 = ilog2(g.B1);
+    t.goff.assign(g.ngroups + 1, 0);
+    for (int m = 0; m < M; ++m) t.goff[((omega[m] & mask1) >> logB1) + 1]++;
+    for (int q = 0; q < g.ngroups; ++q) t.goff[q + 1] += t.goff[q];
+    std::vector<int32_t> fill(t.goff.begin(), t.goff.end() - 1);
+    for (int m = 0; m < M; ++m) {
+      const int q = (omega[m] & mask1) >> logB1;
+      const int p = fill[q]++;
+      t.perm[p] = m;
+      t.ent_k[p] = omega[m];
+    }
+  }
+  // twiddles e^{+2 pi i q / N}: lo for q < 2^twS, hi for q * 2^twS, q < N >> twS
+  const int nlo = 1 << g.twS, nhi = g.N >> g.twS;
+  t.tw64.resize(nlo + nhi);
+  t.tw32.resize(nlo + nhi);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int q = 0; q < nlo + nhi; ++q) {
+    const long double k = q < nlo ? (long double)q : (long double)(q - nlo) * nlo;
+    const long double a = two_pi * k / (long double)g.N;
+    const long double c = cosl(a), s = sinl(a);
+    t.tw64[q] = make_double2((double)c, (double)s);
+    t.tw32[q] = make_float2((float)c, (float)s);
+  }
+}
+
+static int pick_threads(int tile_n) {
+  int t = tile_n / 4;
+  if (t < 64) t = 64;
+  if (t > 256) t = 256;
+  return t;
+}
+
+hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const EntDev& en,
+                         const XSrc& in, const XDst& out, void* tmp, const Status* status,
+                         hipStream_t st, int ninst, int64_t isn, int64_t ism, int64_t isp,
+                         int64_t isx, int64_t isg) {
+  const bool fft = g.fourier;
+  XParams p{};
+  p.N = g.N;
+  p.logN = g.logN;
+  p.twS = g.twS;
+  p.sign = sign;
+  p.tw_lo = tw.lo;
+  p.tw_hi = tw.hi;
+  p.status = status;
+  p.excl = out.excl;
+  p.inst_excl = isx;
+  p.inst_goff = isg;
+  if (single_ok(vk, g.N)) {
+    p.L = g.N; p.logL = g.logN; p.B = 1;
+    p.in_mode = in.mode; p.in_kind = in.kind; p.in = in.ptr;
+    p.in_ss = 0; p.in_es = 1;
+    p.ent_k = en.ent_k; p.goff = nullptr; p.nent = en.M; p.logN1 = 0;
+    p.inst_in = in.mode == IN_DENSE ? isn : ism;
+    p.inst_ent = ism;
+    p.out = out.out; p.out_kind = out.out ? out.kind : -1;
+    p.out2 = out.out2; p.out2_kind = out.out2 ? out.kind2 : -1;
+    p.out_ss = 0; p.out_es = 1;
+    p.inst_out = isn; p.inst_out2 = isn;
+    p.inter_tw = 0;
+    p.scale = out.scale;
+    p.partial = out.partial; p.inst_part = isp;
+    p.nthreads = pick_threads(g.N);
+    return launch_xform(vk, fft, p, 1, ninst, st);
+  }
+  const int N1 = 1 << g.n1, N2 = 1 << g.n2;
+  // pass 1: N1 sequences (columns k1) of length N2 over k2
+  XParams a = p;
+  a.L = N2; a.logL = g.n2; a.B = g.B1;
+  a.in_mode = in.mode; a.in_kind = in.kind; a.in = in.ptr;
+  a.in_ss = 1; a.in_es = N1;
+  a.ent_k = en.ent_k; a.goff = en.goff; a.nent = en.M; a.logN1 = g.n1;
+  a.inst_in = in.mode == IN_DENSE ? isn : ism;
+  a.inst_ent = ism;
+  a.out = tmp; a.out_kind = vk; a.out2 = nullptr; a.out2_kind = -1;
+  a.out_ss = 1; a.out_es = N1; a.inst_out = isn; a.inst_out2 = 0;
+  a.inter_tw = fft ? 1 : 0;
+  a.scale = 1.0;
+  a.partial = nullptr; a.excl = nullptr;
+  a.nthreads = pick_threads(a.L * a.B);
+  hipError_t e = launch_xform(vk, fft, a, N1 / g.B1, ninst, st);
+  if (e != hipSuccess) return e;
+  // pass 2: N2 sequences (rows j2) of length N1 over k1
+  XParams b = p;
+  b.L = N1; b.logL = g.n1; b.B = g.B2;
+  b.in_mode = IN_DENSE; b.in_kind = vk; b.in = tmp;
+  b.in_ss = N1; b.in_es = 1; b.inst_in = isn;
+  b.ent_k = nullptr; b.goff = nullptr; b.nent = 0; b.logN1 = 0; b.inst_ent = 0;
+  b.out = out.out; b.out_kind = out.out ? out.kind : -1;
+  b.out2 = out.out2; b.out2_kind = out.out2 ? out.kind2 : -1;
+  if (fft) { b.out_ss = 1; b.out_es = N2; }
+  else { b.out_ss = N1; b.out_es = 1; }
+  b.inst_out = isn; b.inst_out2 = isn;
+  b.inter_tw = 0;
+  b.scale = out.scale;
+  b.partial = out.partial; b.inst_part = isp;
+  b.nthreads = pick_threads(b.L * b.B);
+  return launch_xform(vk, fft, b, N2 / g.B2, ninst, st);
+}
+
+int validate_problem(const fcmp_problem* p, bool need_k) {
+  if (!p) return set_error(FCMP_E_INVALID, "problem is NULL");
+  if (p->matrix_class != FCMP_HADAMARD && p->matrix_class != FCMP_FOURIER)
+    return set_error(FCMP_E_INVALID, "matrix_class must be FCMP_HADAMARD or FCMP_FOURIER");
+  const int64_t N = p->N, M = p->M, K = p->K;
+  if (N < 2 || N > (int64_t(1) << 24) || (N & (N - 1)) != 0)
+    return set_error(FCMP_E_INVALID, "N must be a power of two in [2, 2^24]");
+  if (p->matrix_class == FCMP_FOURIER && N > (int64_t(1) << 22))
+    return set_error(FCMP_E_INVALID, "Fourier N must be <= 2^22");
+  if (M < 1 || M > N) return set_error(FCMP_E_INVALID, "M must be in [1, N]");
+  if (need_k && (K < 1 || K >= M))
+    return set_error(FCMP_E_INVALID, "K must be in [1, M-1]");
+  if (!p->omega) return set_error(FCMP_E_INVALID, "omega is NULL");
+  int32_t prev = -1;
+  for (int64_t m = 0; m < M; ++m) {
+    const int32_t k = p->omega[m];
+    if (k < 0 || k >= N) return set_error(FCMP_E_INVALID, "omega entry out of [0, N)");
+    if (k <= prev) return set_error(FCMP_E_INVALID, "omega must be strictly increasing");
+    prev = k;
+  }
+  return FCMP_OK;
+}
+
+int validate_options(const fcmp_problem* p, const fcmp_options* o) {
+  if (!o) return set_error(FCMP_E_INVALID, "options is NULL");
+  if (o->algorithm < FCMP_OMP || o->algorithm > FCMP_COSAMP)
+    return set_error(FCMP_E_INVALID, "unknown algorithm");
+  if (o->corr_method < FCMP_CORR_CONVENTIONAL || o->corr_method > FCMP_CORR_ADAPTIVE)
+    return set_error(FCMP_E_INVALID, "unknown corr_method");
+  if (o->corr_precision != FCMP_FP64 && o->corr_precision != FCMP_FP32)
+    return set_error(FCMP_E_INVALID, "unknown corr_precision");
+  if (o->max_iter < 0) return set_error(FCMP_E_INVALID, "max_iter must be >= 0");
+  if (o->switch_t < 0) return set_error(FCMP_E_INVALID, "switch_t must be >= 0");
+  if (o->res_tol != 0.0) return set_error(FCMP_E_INVALID, "res_tol is reserved and must be 0");
+  if (o->algorithm == FCMP_OMP && p->K > 4096)
+    return set_error(FCMP_E_INVALID, "OMP supports K <= 4096");
+  if (o->algorithm == FCMP_SP && 2 * p->K > p->M)
+    return set_error(FCMP_E_INVALID, "SP needs 2K <= M");
+  if (o->algorithm == FCMP_COSAMP && 3 * p->K > p->M)
+    return set_error(FCMP_E_INVALID, "CoSaMP needs 3K <= M");
+  return FCMP_OK;
+}
+
+}  // namespace fcmp

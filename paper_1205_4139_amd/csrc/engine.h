@@ -1,0 +1,74 @@
+// Host-side engine: validation, transform geometry, workspace layout and
+// launch sequencing behind the C ABI.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/fcmp.h"
+#include "kernels.h"
+
+namespace fcmp {
+
+int set_error(int code, const std::string& msg);
+const char* last_error();
+
+// Transform geometry for one N: single workgroup when the values fit in LDS,
+// else two passes N = N1 * N2 with B1 (pass 1) / B2 (pass 2) sequences per
+// workgroup.  Entries (rows of Phi) are grouped by pass-1 workgroup when any
+// FP64 transform of this N needs two passes.
+struct Geo {
+  int N = 0, logN = 0, twS = 0;
+  bool fourier = false;
+  int n1 = 0, n2 = 0;        // log2 N1, log2 N2
+  int B1 = 1, B2 = 1;
+  bool grouped = false;
+  int ngroups = 1;           // pass-1 workgroups = N1 / B1
+};
+
+bool single_ok(int vk, int N);
+Geo make_geo(bool fourier, int N);
+int transform_partials(int vk, const Geo& g);   // partials written by a transform
+
+struct HostTables {
+  std::vector<int32_t> ent_k, perm, goff;   // entry order (grouped or Omega order)
+  std::vector<double2> tw64;                // lo (2^twS) then hi (N >> twS), sign +
+  std::vector<float2> tw32;
+};
+void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t);
+
+struct TwDev { const void* lo; const void* hi; };
+struct EntDev { const int32_t* ent_k; const int32_t* goff; int M; };
+struct XSrc { int mode; int kind; const void* ptr; };
+struct XDst {
+  void* out = nullptr; int kind = -1;
+  void* out2 = nullptr; int kind2 = -1;
+  Sel* partial = nullptr; const uint32_t* excl = nullptr;
+  double scale = 1.0;
+};
+
+// One N-point transform (sign +1: U^H, -1: U) of the zero-filled entries or
+// of a dense N-vector.  tmp: N values of kind vk (two-pass only).
+hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const EntDev& en,
+                         const XSrc& in, const XDst& out, void* tmp, const Status* status,
+                         hipStream_t st, int ninst = 1, int64_t inst_stride_n = 0,
+                         int64_t inst_stride_m = 0, int64_t inst_stride_part = 0,
+                         int64_t inst_stride_excl = 0, int64_t inst_stride_goff = 0);
+
+// Workspace carving helper (256-byte aligned regions).
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <class T> T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  void* take_bytes(size_t bytes) { return take<char>(bytes); }
+  size_t total() const { return (off + 255) & ~(size_t)255; }
+};
+
+int validate_problem(const fcmp_problem* p, bool need_k);
+int validate_options(const fcmp_problem* p, const fcmp_options* o);
+
+}  // namespace fcmp

@@ -1,0 +1,134 @@
+// The paper's fast correlation, eq. (kernelsum) / (kernelsumOMP):
+//   h(j) = h_0(j) - sum_tau x(tau) (P_{lam_tau} c)(j),
+// where P_lambda (Thm 2-1) is the cyclic shift c((j - lambda) mod N) for the
+// Fourier class and the dyadic shift c(j XOR lambda) for the Hadamard class
+// (Sec. III-B).  h_0 and the taps are FP64, the kernel vector c is stored in
+// the correlation precision and every product is accumulated in FP64.  Lanes
+// of a wave take consecutive j, so each tap's gather of c is one contiguous
+// (shift) or in-block-permuted (XOR) 64-element run.  The identification
+// argmax over the columns not yet selected is fused into the epilogue.
+#include "kernels.h"
+
+namespace fcmp {
+
+constexpr int F_THREADS = 256;
+constexpr int F_TCH = 1024;   // taps staged in LDS per chunk
+
+template <class VC> __device__ __forceinline__ double cwiden(VC v);
+template <> __device__ __forceinline__ double cwiden<float>(float v) { return (double)v; }
+template <> __device__ __forceinline__ double cwiden<double>(double v) { return v; }
+template <class VC> __device__ __forceinline__ double2 cwiden2(VC v);
+template <> __device__ __forceinline__ double2 cwiden2<float2>(float2 v) {
+  return make_double2((double)v.x, (double)v.y);
+}
+template <> __device__ __forceinline__ double2 cwiden2<double2>(double2 v) { return v; }
+
+template <class VC, int JPT>
+__global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
+  constexpr bool FOURIER = VT<VC>::cplx;
+  using Wd = typename VT<VC>::Wide;
+  __shared__ int32_t sl[F_TCH];
+  __shared__ Wd sx[F_TCH];
+  __shared__ Sel red[16];
+  const int inst = blockIdx.y;
+  if (p.status && p.status[inst].done) return;
+  const int tid = threadIdx.x;
+  const uint32_t mask = (uint32_t)p.N - 1u;
+  const int64_t jb = (int64_t)blockIdx.x * (F_THREADS * JPT) + tid;
+  const Wd* h0 = (const Wd*)p.h0 + (int64_t)inst * p.inst_h0;
+  const VC* c = (const VC*)p.c + (int64_t)inst * p.inst_c;
+  const int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
+  const Wd* xg = (const Wd*)p.x + (int64_t)inst * p.inst_x;
+  Wd acc[JPT];
+#pragma unroll
+  for (int u = 0; u < JPT; ++u) {
+    const int64_t j = jb + (int64_t)u * F_THREADS;
+    acc[u] = j < p.N ? h0[j] : vzero(Wd());
+  }
+  for (int base = 0; base < p.ntaps; base += F_TCH) {
+    const int n = min(F_TCH, p.ntaps - base);
+    __syncthreads();
+    for (int e = tid; e < n; e += F_THREADS) {
+      sl[e] = lam[base + e];
+      sx[e] = xg[base + e];
+    }
+    __syncthreads();
+    for (int tau = 0; tau < n; ++tau) {
+      const uint32_t l = (uint32_t)sl[tau];
+      const Wd xv = sx[tau];
+      VC cv[JPT];
+#pragma unroll
+      for (int u = 0; u < JPT; ++u) {
+        const uint32_t j = (uint32_t)(jb + u * F_THREADS) & mask;
+        cv[u] = c[perm_index(FOURIER, j, l, mask)];
+      }
+#pragma unroll
+      for (int u = 0; u < JPT; ++u) {
+        if constexpr (FOURIER) {
+          const double2 cw = cwiden2<VC>(cv[u]);
+          acc[u].x -= xv.x * cw.x - xv.y * cw.y;
+          acc[u].y -= xv.x * cw.y + xv.y * cw.x;
+        } else {
+          acc[u] -= xv * cwiden<VC>(cv[u]);
+        }
+      }
+    }
+  }
+  double bkey = -1.0;
+  int64_t bidx = -1;
+  const uint32_t* excl = p.excl ? p.excl + (int64_t)inst * p.inst_excl : nullptr;
+  Wd* hout = p.h ? (Wd*)p.h + (int64_t)inst * p.inst_h : nullptr;
+#pragma unroll
+  for (int u = 0; u < JPT; ++u) {
+    const int64_t j = jb + (int64_t)u * F_THREADS;
+    if (j < p.N) {
+      if (hout) hout[j] = acc[u];
+      if (p.partial && (!excl || !bit_is_set(excl, j))) {
+        const double kk = vmag2(acc[u]);
+        if (sel_better(kk, j, bkey, bidx)) { bkey = kk; bidx = j; }
+      }
+    }
+  }
+  if (p.partial) {
+    const Sel r = block_sel_reduce(bkey, bidx, red);
+    if (tid == 0) p.partial[(int64_t)inst * p.inst_part + blockIdx.x] = r;
+  }
+}
+
+static int jpt_for(int N) {
+  // enough workgroups to cover the chip for one instance, wider tiles beyond
+  if (N <= (1 << 17)) return 1;
+  if (N <= (1 << 19)) return 2;
+  return 4;
+}
+
+int fastcorr_groups(int N) {
+  const int jpt = jpt_for(N);
+  return (N + F_THREADS * jpt - 1) / (F_THREADS * jpt);
+}
+
+template <class VC>
+static hipError_t launch_v(const FParams& p, int ninst, hipStream_t st) {
+  const int jpt = jpt_for(p.N);
+  const int groups = fastcorr_groups(p.N);
+  dim3 grid(groups, ninst);
+  switch (jpt) {
+    case 1: hipLaunchKernelGGL((fastcorr_kernel<VC, 1>), grid, dim3(F_THREADS), 0, st, p); break;
+    case 2: hipLaunchKernelGGL((fastcorr_kernel<VC, 2>), grid, dim3(F_THREADS), 0, st, p); break;
+    default: hipLaunchKernelGGL((fastcorr_kernel<VC, 4>), grid, dim3(F_THREADS), 0, st, p); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fastcorr(const FParams& p, int ninst, int* groups_out, hipStream_t st) {
+  if (groups_out) *groups_out = fastcorr_groups(p.N);
+  switch (p.c_kind) {
+    case V_F32: return launch_v<float>(p, ninst, st);
+    case V_F64: return launch_v<double>(p, ninst, st);
+    case V_C64: return launch_v<float2>(p, ninst, st);
+    case V_C128: return launch_v<double2>(p, ninst, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fcmp

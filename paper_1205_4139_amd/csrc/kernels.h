@@ -1,0 +1,132 @@
+// Launch interfaces of the HIP kernels (host side).
+#pragma once
+#include "common.h"
+
+namespace fcmp {
+
+enum VKind { V_F32 = 0, V_F64 = 1, V_C64 = 2, V_C128 = 3 };
+
+inline size_t vbytes(int vk) { return vk == V_F32 ? 4 : (vk == V_C128 ? 16 : 8); }
+inline bool vcomplex(int vk) { return vk >= V_C64; }
+inline int vwide(int vk) { return vcomplex(vk) ? V_C128 : V_F64; }
+inline int vnarrow_kind(int vk) { return vcomplex(vk) ? V_C64 : V_F32; }
+
+// ------------------------------------------------------------------ transforms
+// One kernel runs B length-L transforms per workgroup through LDS.  Element
+// (s, i) of a sequence s is read from in[s*in_ss + i*in_es] (dense input) or
+// scattered from a list of (k, value) entries (sparse input: the zero-filled
+// residual of the correlation step); output element (s, j) goes to
+// out[s*out_ss + j*out_es].  The FFT is the in-place decimation-in-time form
+// (bit-reversed placement on input, natural order out); the WHT is the
+// in-place natural-order form.  The identification argmax can be fused into
+// the output loop.
+enum InMode { IN_DENSE = 0, IN_SPARSE = 1, IN_SPARSE_ONES = 2 };
+
+struct XParams {
+  int L, logL, B;          // transform length and sequences per workgroup
+  int N, logN, twS;        // problem size; twiddle table split
+  int sign;                // +1: e^{+2 pi i ...} (U^H), -1: e^{-2 pi i ...} (U)
+  int in_mode;
+  int in_kind;             // VKind of the input values
+  const void* in;
+  int64_t in_ss, in_es;
+  const int32_t* ent_k;    // sparse: k of each entry (entry order)
+  const int32_t* goff;     // sparse: per-workgroup entry ranges; NULL: all entries
+  int32_t nent;
+  int logN1;               // sparse: k -> (i = k >> logN1, s = k & (N1-1))
+  void* out;  int out_kind;    // -1: none
+  void* out2; int out2_kind;   // -1: none
+  int64_t out_ss, out_es;
+  int inter_tw;            // multiply output (s, j) by W_N^{s j}
+  double scale;
+  Sel* partial;            // nullable: one (key, idx) per workgroup
+  const uint32_t* excl;    // nullable exclusion bitmap (global h index)
+  const void* tw_lo;       // twiddles in the transform precision, sign +
+  const void* tw_hi;
+  const Status* status;    // nullable: skip when status[inst].done
+  // per-instance strides (blockIdx.y), in elements of each array
+  int64_t inst_in, inst_ent, inst_goff, inst_out, inst_out2, inst_part, inst_excl;
+  int nthreads;
+};
+
+// vk: VKind of the transform arithmetic; fft: Fourier (else Hadamard)
+hipError_t launch_xform(int vk, bool fft, const XParams& p, int groups, int ninst,
+                        hipStream_t st);
+size_t xform_lds_bytes(int vk, bool fft, int L, int B, int N, int twS);
+
+// ------------------------------------------------------------------ residual
+// r[e] = y[e] - sum_tau U(k_e, lam_tau) x_tau for the current support, in FP64,
+// stored in the correlation precision (Algorithm 1.1, step 7).
+struct RParams {
+  int N, logN, twS;
+  int fourier;
+  int32_t M;
+  const int32_t* ent_k;    // entry order
+  const void* y;           // FP64 (wide) in entry order
+  void* r;  int r_kind;    // output
+  const int32_t* lam;      // selected columns
+  const void* x;           // FP64 (wide) coefficients
+  int ntaps;
+  const void* tw_lo;       // FP64 twiddles, sign +
+  const void* tw_hi;
+  const Status* status;
+  int64_t inst_ent, inst_y, inst_r, inst_lam, inst_x;
+};
+hipError_t launch_residual(const RParams& p, int ninst, hipStream_t st);
+
+// ------------------------------------------------------------------ fast path
+// h(j) = h0(j) - sum_tau x_tau c((j - lam_tau) mod N) (Fourier) or
+// c(j XOR lam_tau) (Hadamard), eq. (kernelsum); FP64 accumulation.
+struct FParams {
+  int N, logN;
+  int fourier;
+  int c_kind;              // VKind of the stored kernel vector
+  const void* h0;          // FP64 (wide)
+  const void* c;
+  const int32_t* lam;
+  const void* x;           // FP64 (wide)
+  int ntaps;
+  void* h;                 // nullable FP64 (wide) output
+  Sel* partial;
+  const uint32_t* excl;
+  const Status* status;
+  int64_t inst_h0, inst_c, inst_lam, inst_x, inst_h, inst_part, inst_excl;
+};
+hipError_t launch_fastcorr(const FParams& p, int ninst, int* groups_out, hipStream_t st);
+int fastcorr_groups(int N);
+
+// ------------------------------------------------------------------ least squares
+// Selects lambda_t from the partials, appends it to the support, extends the
+// inverse Cholesky factor W = L^{-1} of the Gram by one row, updates z = W b
+// and x = W^H z (Algorithm 1.1, steps 3-6).
+struct LParams {
+  int N;
+  int fourier;
+  int t;                   // this call makes selection number t (1-based)
+  const Sel* partial;  int npart;
+  const void* c64;         // FP64 kernel vector (Gram entries)
+  const void* h0;          // FP64 h_0 = Phi^H y (right-hand side b = h0(Lambda))
+  void* W;                 // packed rows, t(t+1)/2 entries
+  void* z;  void* x;
+  int32_t* lam;
+  uint32_t* excl;
+  Status* status;
+  int64_t inst_part, inst_c, inst_h0, inst_W, inst_z, inst_x, inst_lam, inst_excl;
+};
+hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st);
+
+// ------------------------------------------------------------------ utilities
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_gather_wide(int vk, const void* src, const int32_t* idx, void* dst,
+                              int64_t n, int64_t inst_src, int64_t inst_idx, int64_t inst_dst,
+                              int ninst, hipStream_t st);
+hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam,
+                           const void* x, int K, int32_t* support_out, void* x_out,
+                           hipStream_t st);
+hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st);
+hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier,
+                              int64_t inst_y, int ninst, hipStream_t st);
+hipError_t launch_noise(int fourier, const void* clean, const void* noise, double snr_db,
+                        void* y, int M, hipStream_t st);
+
+}  // namespace fcmp

@@ -1,0 +1,138 @@
+// Small helper kernels: fills, gathers, status initialisation, result copy-out,
+// the final reduction of identification partials and measurement noise.
+#include "kernels.h"
+
+namespace fcmp {
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t groups = (n + 255) / 256;
+  if (groups > 4096) groups = 4096;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)groups), dim3(256), 0, st, p, v, n);
+  return hipGetLastError();
+}
+
+template <class Wd>
+__global__ void gather_kernel(const Wd* src, const int32_t* idx, Wd* dst, int64_t n,
+                              int64_t is, int64_t ii, int64_t id) {
+  const int inst = blockIdx.y;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[inst * id + e] = src[inst * is + idx[inst * ii + e]];
+}
+
+hipError_t launch_gather_wide(int vk, const void* src, const int32_t* idx, void* dst,
+                              int64_t n, int64_t is, int64_t ii, int64_t id, int ninst,
+                              hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t groups = (n + 255) / 256;
+  if (groups > 2048) groups = 2048;
+  dim3 grid((unsigned)groups, ninst);
+  const size_t eb = vbytes(vk);
+  if (eb == 16)
+    hipLaunchKernelGGL(gather_kernel<double2>, grid, dim3(256), 0, st, (const double2*)src, idx,
+                       (double2*)dst, n, is, ii, id);
+  else if (eb == 8)
+    hipLaunchKernelGGL(gather_kernel<uint64_t>, grid, dim3(256), 0, st, (const uint64_t*)src,
+                       idx, (uint64_t*)dst, n, is, ii, id);
+  else
+    hipLaunchKernelGGL(gather_kernel<uint32_t>, grid, dim3(256), 0, st, (const uint32_t*)src,
+                       idx, (uint32_t*)dst, n, is, ii, id);
+  return hipGetLastError();
+}
+
+template <class Wd>
+__global__ void finalize_kernel(const Status* status, const int32_t* lam, const Wd* x, int K,
+                                int32_t* sup, Wd* xo) {
+  const int it = status->iterations;
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < K; i += blockDim.x * gridDim.x) {
+    const bool ok = i < it;
+    sup[i] = ok ? lam[i] : -1;
+    xo[i] = ok ? x[i] : vzero(Wd());
+  }
+}
+
+hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam, const void* x,
+                           int K, int32_t* sup, void* xo, hipStream_t st) {
+  const int groups = (K + 255) / 256;
+  if (fourier)
+    hipLaunchKernelGGL(finalize_kernel<double2>, dim3(groups), dim3(256), 0, st, status, lam,
+                       (const double2*)x, K, sup, (double2*)xo);
+  else
+    hipLaunchKernelGGL(finalize_kernel<double>, dim3(groups), dim3(256), 0, st, status, lam,
+                       (const double*)x, K, sup, (double*)xo);
+  return hipGetLastError();
+}
+
+__global__ void reduce_sel_kernel(const Sel* partial, int n, Sel* out) {
+  __shared__ Sel red[16];
+  double bk = -1.0;
+  int64_t bi = -1;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const Sel s = partial[e];
+    if (s.idx >= 0 && sel_better(s.key, s.idx, bk, bi)) { bk = s.key; bi = s.idx; }
+  }
+  const Sel r = block_sel_reduce(bk, bi, red);
+  if (threadIdx.x == 0) *out = r;
+}
+
+hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_sel_kernel, dim3(1), dim3(256), 0, st, partial, n, out);
+  return hipGetLastError();
+}
+
+// status[inst] = {0...}, ynorm2 = ||y||^2 (one workgroup per instance)
+__global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, int64_t inst_y) {
+  __shared__ double dred[16];
+  const int inst = blockIdx.x;
+  const double* yi = y + (int64_t)inst * inst_y;
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < nreal; e += blockDim.x) s += yi[e] * yi[e];
+  s = block_sum(s, dred);
+  if (threadIdx.x == 0) {
+    Status z;
+    z.done = 0; z.numeric = 0; z.iterations = 0; z.pad = 0;
+    z.znorm2 = 0.0; z.ynorm2 = s; z.last_key = 0.0; z.pad2 = 0.0;
+    st[inst] = z;
+  }
+}
+
+hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier, int64_t inst_y,
+                              int ninst, hipStream_t st) {
+  const int64_t nreal = fourier ? 2 * (int64_t)M : M;
+  const int64_t istride = fourier ? 2 * inst_y : inst_y;
+  hipLaunchKernelGGL(init_status_kernel, dim3(ninst), dim3(256), 0, st, st_dev,
+                     (const double*)y, nreal, istride);
+  return hipGetLastError();
+}
+
+// y = clean + g * ||clean|| / ||g|| * 10^(-snr/20), one workgroup (M real or complex)
+__global__ void noise_kernel(const double* clean, const double* g, double snr_db, double* y,
+                             int64_t nreal) {
+  __shared__ double dred[16];
+  double a = 0.0, b = 0.0;
+  for (int64_t e = threadIdx.x; e < nreal; e += blockDim.x) {
+    a += clean[e] * clean[e];
+    b += g[e] * g[e];
+  }
+  a = block_sum(a, dred);
+  b = block_sum(b, dred);
+  const double sc = (b > 0.0) ? sqrt(a / b) * pow(10.0, -snr_db / 20.0) : 0.0;
+  for (int64_t e = threadIdx.x; e < nreal; e += blockDim.x) y[e] = clean[e] + g[e] * sc;
+}
+
+hipError_t launch_noise(int fourier, const void* clean, const void* noise, double snr_db, void* y,
+                        int M, hipStream_t st) {
+  const int64_t nreal = fourier ? 2 * (int64_t)M : M;
+  hipLaunchKernelGGL(noise_kernel, dim3(1), dim3(1024), 0, st, (const double*)clean,
+                     (const double*)noise, snr_db, (double*)y, nreal);
+  return hipGetLastError();
+}
+
+}  // namespace fcmp

@@ -1,0 +1,70 @@
+"""GPU OMP solves (Algorithm 1.1) against the FP64 oracle: supports must match
+exactly on instances whose identification gaps are certified at the
+correlation precision, and x must agree to 1e-10 relative."""
+import numpy as np
+import pytest
+
+import instancegen
+import oracle
+from oracle import certify
+from tests.gpu_util import lib, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # cls, N, M, K, law, snr
+    ("H", 1024, 256, 16, "gauss", None),
+    ("F", 1024, 256, 16, "cgauss", 30.0),
+    ("H", 4096, 1000, 37, "gauss", 40.0),
+    ("F", 16384, 4096, 40, "cgauss", 30.0),
+    ("H", 65536, 8192, 60, "pm_u12", None),
+    ("F", 65536, 16384, 64, "cgauss", 30.0),
+]
+METHODS = ["conventional", "fast", "adaptive"]
+
+
+@pytest.fixture(scope="module")
+def fc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib()
+
+
+_REF = {}
+
+
+def _reference(case, seed):
+    key = (case, seed)
+    if key not in _REF:
+        cls, N, M, K, law, snr = case
+        inst = instancegen.draw_instance(cls, N, M, K, law, snr, seed)
+        y = oracle.problem.instance_measure(inst, tier="transform")
+        op = oracle.make_operator(cls, N, inst.omega)
+        ref = oracle.omp(op, y, K)
+        _REF[key] = (inst, y, ref)
+    return _REF[key]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}{c[1]}-{c[3]}")
+def test_omp_parity(fc, case, method, precision):
+    checked = 0
+    for seed in range(3):
+        inst, y, ref = _reference(case, 7000 + seed)
+        if not certify.certified(ref, precision):
+            continue
+        res = fc.solve(inst.cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y),
+                       method=method, precision=precision)
+        sup = to_np(res.support)
+        x = to_np(res.x)
+        assert res.stats.status == 0
+        assert res.stats.iterations == inst.K
+        assert list(sup) == list(ref.support)
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+        # the library reports ||r|| from the normal equations, ||y||^2 - ||z||^2,
+        # whose absolute accuracy is eps ||y||^2 on the squared norm
+        assert abs(res.stats.res_norm ** 2 - ref.res_norm ** 2) <= 1e-12 * np.linalg.norm(y) ** 2
+        checked += 1
+    assert checked >= 1

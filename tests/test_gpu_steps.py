@@ -1,0 +1,161 @@
+"""GPU parity of the single steps of the hot path against the FP64 oracle:
+kernel vector (A1), conventional correlation with fused identification
+(A3 + A5), fast correlation (A4 + A5) and the forward operator."""
+import numpy as np
+import pytest
+
+import oracle
+from tests.gpu_util import inf_rel, lib, omega, rand_vec, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+# (N, M): single-workgroup sizes, two-pass sizes, ragged M
+SIZES = [(2, 1), (16, 5), (1024, 256), (4096, 1000), (16384, 4096), (65536, 16384),
+         (1 << 18, 1 << 15)]
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def fc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib()
+
+
+def _cplx(cls):
+    return cls == "F"
+
+
+@pytest.mark.parametrize("cls", ["H", "F"])
+@pytest.mark.parametrize("N,M", SIZES)
+def test_kernel_vector(fc, cls, N, M):
+    rng = np.random.default_rng(N + M)
+    om = omega(rng, N, M)
+    want = oracle.kernel_vector(cls, N, om, "transform")
+    c64, cp = fc.kernel_vector(cls, N, om, "fp32")
+    c64 = to_np(c64)
+    cp = to_np(cp)
+    assert inf_rel(c64, want) <= TOL["fp64"]
+    assert inf_rel(cp, want) <= 1e-6
+    if cls == "H":
+        # N c is an integer: the FP64 result is exact
+        assert np.array_equal(c64 * N, np.round(want * N))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cls", ["H", "F"])
+@pytest.mark.parametrize("N,M", SIZES)
+def test_correlate(fc, cls, N, M, precision):
+    rng = np.random.default_rng(3 * N + M)
+    om = omega(rng, N, M)
+    r = rand_vec(rng, M, _cplx(cls))
+    want = oracle.unitary.TransformOperator(cls, N, om).adjoint(r)
+    rd = to_dev(r.astype(np.complex64 if (_cplx(cls) and precision == "fp32") else
+                         np.float32 if precision == "fp32" else r.dtype))
+    h, sel = fc.correlate(cls, N, om, rd, precision)
+    h = to_np(h)
+    # the oracle sees the same (rounded) input the GPU saw
+    rin = to_np(rd).astype(np.complex128 if _cplx(cls) else np.float64)
+    want = oracle.unitary.TransformOperator(cls, N, om).adjoint(rin)
+    assert inf_rel(h, want) <= TOL[precision]
+    idx, key = fc.decode_sel(sel)
+    a = np.abs(want) ** 2
+    order = np.argsort(-a, kind="stable")
+    gap = (np.sqrt(a[order[0]]) - np.sqrt(a[order[1]])) / np.sqrt(a[order[0]]) if N > 1 else 1
+    if gap >= 2.5 * TOL[precision]:
+        assert idx == order[0]
+    else:
+        assert np.sqrt(a[idx]) >= np.sqrt(a[order[0]]) * (1 - 2 * TOL[precision])
+
+
+@pytest.mark.parametrize("N", [1024, 65536, 1 << 20])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_correlate_hadamard_integer_bitexact(fc, N, precision):
+    """N = 4^m: integer residuals give exactly representable correlations, so
+    the GPU must match the oracle bit for bit."""
+    rng = np.random.default_rng(N)
+    M = N // 8
+    om = omega(rng, N, M)
+    r = rng.integers(-6, 7, M).astype(np.float64)
+    want = oracle.unitary.TransformOperator("H", N, om).adjoint(r)
+    rd = to_dev(r.astype(np.float32) if precision == "fp32" else r)
+    h, sel = fc.correlate("H", N, om, rd, precision)
+    assert np.array_equal(to_np(h).astype(np.float64), want)
+
+
+def test_correlate_ties_lowest_index(fc):
+    """A single nonzero residual entry: every |h(j)| is equal, so the lowest
+    eligible index wins; the exclusion bitmap removes columns."""
+    import torch
+    N, M = 1024, 64
+    rng = np.random.default_rng(1)
+    om = omega(rng, N, M)
+    r = np.zeros(M)
+    r[7] = 3.0
+    h, sel = fc.correlate("H", N, om, to_dev(r))
+    assert fc.decode_sel(sel)[0] == 0
+    excl = np.zeros(N // 32, dtype=np.uint32)
+    excl[0] = 0x1F          # columns 0..4 excluded
+    ex = torch.from_numpy(excl.view(np.int32)).cuda()
+    h, sel = fc.correlate("H", N, om, to_dev(r), excl=ex)
+    assert fc.decode_sel(sel)[0] == 5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cls", ["H", "F"])
+@pytest.mark.parametrize("N,M,T", [(64, 20, 3), (1024, 256, 15), (65536, 16384, 255),
+                                   (1 << 20, 1 << 17, 40)])
+def test_fast_correlate(fc, cls, N, M, T, precision):
+    rng = np.random.default_rng(N + T)
+    om = omega(rng, N, M)
+    y = rand_vec(rng, M, _cplx(cls))
+    op = oracle.unitary.TransformOperator(cls, N, om)
+    h0 = op.adjoint(y)
+    c = oracle.kernel_vector(cls, N, om, "transform")
+    lam = rng.choice(N, T, replace=False).astype(np.int32)
+    xt = rand_vec(rng, T, _cplx(cls)) * 0.3
+    cp_np = c.astype(np.complex64 if _cplx(cls) else np.float32) if precision == "fp32" else c
+    want = oracle.fast_correlation(cls, N, h0, cp_np.astype(c.dtype), lam, xt)
+    h, sel = fc.fast_correlate(cls, N, to_dev(h0), to_dev(cp_np), to_dev(lam), to_dev(xt),
+                               precision)
+    h = to_np(h)
+    # FP64 accumulation of the same rounded kernel vector: FP64-level agreement
+    assert inf_rel(h, want) <= TOL["fp64"] * max(1, T)
+    # against the exact kernel vector the FP32 storage error stays in tolerance
+    exact = oracle.fast_correlation(cls, N, h0, c, lam, xt)
+    assert inf_rel(h, exact) <= TOL[precision]
+    idx, _ = fc.decode_sel(sel)
+    a = np.abs(want) ** 2
+    assert idx == int(np.argmax(a))
+
+
+def test_fast_correlate_hadamard_integer_bitexact(fc):
+    N, M, T = 4096, 1024, 50
+    rng = np.random.default_rng(9)
+    om = omega(rng, N, M)
+    y = rng.integers(-5, 6, M).astype(np.float64)
+    op = oracle.unitary.TransformOperator("H", N, om)
+    h0 = op.adjoint(y)
+    c = oracle.kernel_vector("H", N, om, "transform")
+    lam = rng.choice(N, T, replace=False).astype(np.int32)
+    xt = rng.integers(-3, 4, T).astype(np.float64)
+    want = oracle.fast_correlation("H", N, h0, c, lam, xt)
+    for prec, cp in (("fp64", c), ("fp32", c.astype(np.float32))):
+        h, _ = fc.fast_correlate("H", N, to_dev(h0), to_dev(cp), to_dev(lam), to_dev(xt), prec)
+        assert np.array_equal(to_np(h), want)
+
+
+@pytest.mark.parametrize("cls", ["H", "F"])
+@pytest.mark.parametrize("N,M", [(16, 5), (1024, 256), (65536, 16384)])
+def test_measure(fc, cls, N, M):
+    rng = np.random.default_rng(N)
+    om = omega(rng, N, M)
+    x = rand_vec(rng, N, _cplx(cls))
+    want = oracle.unitary.TransformOperator(cls, N, om).forward(x)
+    y = to_np(fc.measure(cls, N, om, to_dev(x)))
+    assert inf_rel(y, want) <= TOL["fp64"]
+    g = rand_vec(rng, M, _cplx(cls))
+    yn = to_np(fc.measure(cls, N, om, to_dev(x), to_dev(g), 30.0))
+    wn = oracle.measure(cls, N, om, x, g, 30.0, tier="transform")
+    assert inf_rel(yn, wn) <= TOL["fp64"]

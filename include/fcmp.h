@@ -99,9 +99,13 @@ typedef struct {
   int32_t max_iter;          /* SP/CoSaMP outer iterations (0 = 50); OMP runs K */
   int32_t switch_t;          /* ADAPTIVE: last iteration that uses the fast method
                                 (0 = library's tuned value) */
-  int32_t reserved;
+  uint32_t flags;            /* FCMP_FLAG_* */
   double  res_tol;           /* reserved, must be 0 */
 } fcmp_options;
+
+/* fcmp_plan_solve recomputes the kernel vector (A1) instead of reusing the
+ * one the plan stored at creation. */
+#define FCMP_FLAG_RECOMPUTE_KERNEL 1u
 
 typedef struct {
   int32_t iterations;        /* OMP: selections made; SP/CoSaMP: outer iterations */
@@ -142,6 +146,52 @@ int fcmp_batch_solve(int64_t n, const fcmp_problem* probs, const fcmp_options* o
                      const void* const* y_dev, void* ws_dev, size_t ws_bytes,
                      int32_t* const* support_dev, void* const* x_dev,
                      fcmp_stats* stats, void* hip_stream);
+
+/* ---- plans ------------------------------------------------------------ */
+
+/* A plan holds, in the caller's device workspace, what depends on Omega only
+ * -- the rows of Phi in the order the transform kernels consume them and the
+ * correlation kernel vector c, which the paper notes is independent of x and
+ * "stored in advance" (definition after eq. (kernelsum)) -- plus every
+ * per-solve buffer, for n problems of ONE shape (class, N, M, K) solved in
+ * lockstep: each kernel launch of a solve covers all n instances.
+ * probs: HOST array of n problems (each with its own Omega); the options fix
+ * algorithm and correlation precision for the plan's lifetime.  Creation
+ * uploads the tables, computes c and synchronises the stream.  Solves on one
+ * plan must not overlap (they share the workspace). */
+typedef struct fcmp_plan fcmp_plan;
+int fcmp_plan_query_workspace(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
+                              size_t* bytes);
+int fcmp_plan_create(fcmp_plan** out, int64_t n, const fcmp_problem* probs,
+                     const fcmp_options* opt, void* ws_dev, size_t ws_bytes, void* hip_stream);
+/* y_dev / support_dev / x_dev: HOST arrays of n device pointers (layouts as
+ * for fcmp_solve).  opt may differ from the creation options only in
+ * corr_method, switch_t and flags (NULL: creation options).  stats: host
+ * array of n (nullable; when given the call synchronises the stream). */
+int fcmp_plan_solve(fcmp_plan* plan, const fcmp_options* opt, const void* const* y_dev,
+                    int32_t* const* support_dev, void* const* x_dev, fcmp_stats* stats,
+                    void* hip_stream);
+int fcmp_plan_destroy(fcmp_plan* plan);
+
+/* ---- phase timing ------------------------------------------------------ */
+
+/* When enabled, every launch sequence of a phase is bracketed by hipEvents on
+ * the stream it runs on; fcmp_profile_read synchronises those events and
+ * returns the summed device time per phase. */
+#define FCMP_PHASE_KERNEL 0   /* kernel vector c (plan time, or RECOMPUTE flag) */
+#define FCMP_PHASE_H0     1   /* h_0 = Phi^H y and the first identification      */
+#define FCMP_PHASE_CORR   2   /* conventional correlation (all transform passes) */
+#define FCMP_PHASE_FAST   3   /* fast correlation, eq. (kernelsumOMP)            */
+#define FCMP_PHASE_RESID  4   /* residual r = y - Phi_t x_t                       */
+#define FCMP_PHASE_LS     5   /* identification + least-squares update           */
+#define FCMP_PHASE_OTHER  6   /* gathers, status, copy-out                        */
+#define FCMP_NPHASE       8
+typedef struct {
+  double  ms[FCMP_NPHASE];
+  int64_t launches[FCMP_NPHASE];
+} fcmp_profile;
+int fcmp_profile_enable(int enable);
+int fcmp_profile_read(fcmp_profile* out, int reset);
 
 /* ---- single steps of the hot path (each one launch sequence) ---------- */
 

@@ -50,13 +50,22 @@ class Problem(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("algorithm", ctypes.c_int32), ("corr_method", ctypes.c_int32),
                 ("corr_precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("switch_t", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("switch_t", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("res_tol", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("res_norm", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+NPHASE = 8
+PHASES = ["kernel", "h0", "corr", "fast", "resid", "ls", "other"]
+FLAG_RECOMPUTE_KERNEL = 1
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * NPHASE), ("launches", ctypes.c_int64 * NPHASE)]
 
 
 def _load():
@@ -74,6 +83,13 @@ def _load():
         "fcmp_batch_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_batch_solve": ([i64, P, O, ctypes.POINTER(vp), vp, sz, ctypes.POINTER(vp),
                               ctypes.POINTER(vp), ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "fcmp_plan_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_plan_create": ([ctypes.POINTER(vp), i64, P, O, vp, sz, vp], ctypes.c_int),
+        "fcmp_plan_solve": ([vp, O, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                             ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "fcmp_plan_destroy": ([vp], ctypes.c_int),
+        "fcmp_profile_enable": ([ctypes.c_int], ctypes.c_int),
+        "fcmp_profile_read": ([ctypes.POINTER(Profile), ctypes.c_int], ctypes.c_int),
         "fcmp_kernel_vector_workspace": ([P, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_kernel_vector": ([P, i32, vp, vp, vp, sz, vp], ctypes.c_int),
         "fcmp_correlate_workspace": ([P, i32, ctypes.POINTER(sz)], ctypes.c_int),
@@ -108,9 +124,9 @@ def make_problem(cls, N: int, M: int, K: int, omega) -> tuple:
 
 
 def make_options(algorithm="omp", method="conventional", precision="fp64",
-                 max_iter=0, switch_t=0) -> Options:
+                 max_iter=0, switch_t=0, flags=0) -> Options:
     return Options(ALGO.get(algorithm, algorithm), METHOD.get(method, method),
-                   PREC.get(precision, precision), int(max_iter), int(switch_t), 0, 0.0)
+                   PREC.get(precision, precision), int(max_iter), int(switch_t), int(flags), 0.0)
 
 
 # ---------------------------------------------------------------- torch glue
@@ -245,3 +261,105 @@ def measure(cls, N, omega, x, noise=None, snr_db=None):
                             float(snr_db) if use_noise else 0.0, _ptr(y), _ptr(ws), ws.numel(),
                             _stream()))
     return y
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))()
+    for i, v in enumerate(ptrs):
+        arr[i] = v
+    return arr
+
+
+class Plan:
+    """n problems of one shape (class, N, M, K), each with its own Omega,
+    solved in lockstep; the kernel vectors are computed once at creation."""
+
+    def __init__(self, cls, N, M, K, omegas, algorithm="omp", method="conventional",
+                 precision="fp64", switch_t=0, max_iter=0, device="cuda"):
+        torch = _torch()
+        self.cls, self.N, self.M, self.K = cls, int(N), int(M), int(K)
+        self.n = len(omegas)
+        self._oms = [np.ascontiguousarray(np.asarray(o, dtype=np.int32)) for o in omegas]
+        self._probs = (Problem * self.n)()
+        for i, om in enumerate(self._oms):
+            self._probs[i] = Problem(CLASS[cls], 0, self.N, self.M, self.K,
+                                     om.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self.opt = make_options(algorithm, method, precision, max_iter, switch_t)
+        self.algorithm, self.precision = algorithm, precision
+        n = ctypes.c_size_t(0)
+        _check(lib.fcmp_plan_query_workspace(self.n, self._probs, ctypes.byref(self.opt),
+                                             ctypes.byref(n)))
+        self.ws_bytes = n.value
+        self.ws = _workspace(n.value, device)
+        self._h = ctypes.c_void_p(0)
+        _check(lib.fcmp_plan_create(ctypes.byref(self._h), self.n, self._probs,
+                                    ctypes.byref(self.opt), _ptr(self.ws), self.ws.numel(),
+                                    _stream()))
+        self.device = device
+        self.support = torch.empty((self.n, self.K), dtype=torch.int32, device=device)
+        self.x = torch.empty((self.n, self.K), dtype=_dtype(cls), device=device)
+
+    def solve(self, ys, method=None, switch_t=0, flags=0, stats=False):
+        """ys: tensor [n, M] (or list of n tensors).  Returns (support [n, K],
+        x [n, K], stats list or None); outputs are overwritten by the next solve."""
+        o = make_options(self.algorithm, method or METHOD_NAME[self.opt.corr_method],
+                         self.precision, self.opt.max_iter, switch_t, flags)
+        if hasattr(ys, "dim") and ys.dim() == 2:
+            yp = [ys.data_ptr() + i * ys.stride(0) * ys.element_size() for i in range(self.n)]
+        else:
+            yp = [t.data_ptr() for t in ys]
+        sp = [self.support.data_ptr() + i * self.K * 4 for i in range(self.n)]
+        xe = self.x.element_size()
+        xp = [self.x.data_ptr() + i * self.K * xe for i in range(self.n)]
+        st = (Stats * self.n)() if stats else None
+        _check(lib.fcmp_plan_solve(self._h, ctypes.byref(o), _ptr_array(yp), _ptr_array(sp),
+                                   _ptr_array(xp), st, _stream()))
+        return self.support, self.x, (list(st) if stats else None)
+
+    def close(self):
+        if self._h:
+            lib.fcmp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+METHOD_NAME = {CONVENTIONAL: "conventional", FAST: "fast", ADAPTIVE: "adaptive"}
+
+
+def profile_enable(on=True):
+    _check(lib.fcmp_profile_enable(1 if on else 0))
+
+
+def profile_read(reset=True) -> dict:
+    pr = Profile()
+    _check(lib.fcmp_profile_read(ctypes.byref(pr), 1 if reset else 0))
+    return {name: (pr.ms[i], int(pr.launches[i])) for i, name in enumerate(PHASES)}
+
+
+def batch_solve(problems, ys, algorithm="omp", method="conventional", precision="fp64",
+                switch_t=0, device="cuda"):
+    """Mixed-shape batch.  problems: list of (cls, N, M, K, omega); ys: list of
+    device tensors.  Returns (supports, xs, stats) as lists."""
+    torch = _torch()
+    n = len(problems)
+    oms = [np.ascontiguousarray(np.asarray(p[4], dtype=np.int32)) for p in problems]
+    probs = (Problem * n)()
+    for i, (cls, N, M, K, _o) in enumerate(problems):
+        probs[i] = Problem(CLASS[cls], 0, int(N), int(M), int(K),
+                           oms[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    o = make_options(algorithm, method, precision, 0, switch_t)
+    nb = ctypes.c_size_t(0)
+    _check(lib.fcmp_batch_query_workspace(n, probs, ctypes.byref(o), ctypes.byref(nb)))
+    ws = _workspace(nb.value, device)
+    sups = [torch.empty(int(p[3]), dtype=torch.int32, device=device) for p in problems]
+    xs = [torch.empty(int(p[3]), dtype=_dtype(p[0]), device=device) for p in problems]
+    st = (Stats * n)()
+    _check(lib.fcmp_batch_solve(n, probs, ctypes.byref(o), _ptr_array([y.data_ptr() for y in ys]),
+                                _ptr(ws), ws.numel(), _ptr_array([t.data_ptr() for t in sups]),
+                                _ptr_array([t.data_ptr() for t in xs]), st, _stream()))
+    return sups, xs, list(st)

@@ -3,6 +3,9 @@
 #include <cstring>
 
 #include "engine.h"
+#include "plan.h"
+#include <map>
+#include <tuple>
 
 using namespace fcmp;
 
@@ -67,139 +70,6 @@ TwDev tw_for(int vk, const Geo& g, const Common& c) {
   return TwDev{c.tw64, c.tw64 + nlo};
 }
 
-// ------------------------------------------------------------------ OMP solve
-struct OmpLayout {
-  Common com;
-  void* y_ent = nullptr;   // wide M (entry order)
-  void* r = nullptr;       // prec M
-  void* c64 = nullptr;     // wide N
-  void* cp = nullptr;      // prec N (aliases c64 for FP64)
-  void* h0 = nullptr;      // wide N
-  int32_t* lam = nullptr;
-  uint32_t* excl = nullptr;
-  void* x = nullptr;
-  void* z = nullptr;
-  void* W = nullptr;
-  Status* status = nullptr;
-  size_t total = 0;
-};
-
-OmpLayout omp_layout(const fcmp_problem* p, const fcmp_options* o, void* base) {
-  const bool F = p->matrix_class == FCMP_FOURIER;
-  const Geo g = make_geo(F, (int)p->N);
-  const int wk = wide_kind(F), pk = prec_kind(F, o->corr_precision);
-  const int64_t N = p->N, M = p->M, K = p->K;
-  Carver cv;
-  cv.base = (char*)base;
-  OmpLayout L;
-  carve_common(cv, g, (int)M, L.com);
-  L.y_ent = cv.take_bytes(M * vbytes(wk));
-  L.r = cv.take_bytes(M * vbytes(pk));
-  L.c64 = cv.take_bytes(N * vbytes(wk));
-  L.cp = pk == wk ? L.c64 : cv.take_bytes(N * vbytes(pk));
-  L.h0 = cv.take_bytes(N * vbytes(wk));
-  L.lam = cv.take<int32_t>(K);
-  L.excl = cv.take<uint32_t>((N + 31) / 32);
-  L.x = cv.take_bytes(K * vbytes(wk));
-  L.z = cv.take_bytes(K * vbytes(wk));
-  L.W = cv.take_bytes((size_t)K * (K + 1) / 2 * vbytes(wk));
-  L.status = cv.take<Status>(1);
-  L.total = cv.total();
-  return L;
-}
-
-int omp_enqueue(const fcmp_problem* prob, const fcmp_options* opt, const void* y_dev,
-                const OmpLayout& L, int32_t* support_dev, void* x_dev, hipStream_t st) {
-  const bool F = prob->matrix_class == FCMP_FOURIER;
-  const Geo g = make_geo(F, (int)prob->N);
-  const int wk = wide_kind(F), pk = prec_kind(F, opt->corr_precision);
-  const int N = (int)prob->N, M = (int)prob->M, K = (int)prob->K;
-  HostTables t;
-  int rc = upload_common(g, prob, L.com, st, t);
-  if (rc) return rc;
-  const EntDev en{L.com.ent_k, L.com.goff, M};
-  HIP_TRY(launch_fill_u32(L.excl, 0u, (N + 31) / 32, st));
-  HIP_TRY(launch_init_status(L.status, y_dev, M, F, 0, 1, st));
-  // y in entry order
-  const void* yent = y_dev;
-  if (g.grouped) {
-    HIP_TRY(launch_gather_wide(wk, y_dev, L.com.perm, L.y_ent, M, 0, 0, 0, 1, st));
-    yent = L.y_ent;
-  }
-  // A1: kernel vector c = U^H 1_Omega / N  (definition after eq. (kernelsum))
-  {
-    XDst d;
-    d.out = L.c64; d.kind = wk;
-    if (L.cp != L.c64) { d.out2 = L.cp; d.kind2 = pk; }
-    d.scale = 1.0 / (double)N;
-    HIP_TRY(run_transform(wk, +1, g, tw_for(wk, g, L.com), en, XSrc{IN_SPARSE_ONES, wk, nullptr},
-                          d, L.com.tmp, nullptr, st));
-  }
-  // A2: h_0 = Phi^H y in FP64, with the first identification fused
-  {
-    XDst d;
-    d.out = L.h0; d.kind = wk;
-    d.partial = L.com.partial; d.excl = L.excl;
-    d.scale = 1.0 / std::sqrt((double)N);
-    HIP_TRY(run_transform(wk, +1, g, tw_for(wk, g, L.com), en, XSrc{IN_SPARSE, wk, yent}, d,
-                          L.com.tmp, nullptr, st));
-  }
-  LParams lp{};
-  lp.N = N; lp.fourier = F;
-  lp.partial = L.com.partial; lp.npart = transform_partials(wk, g);
-  lp.c64 = L.c64; lp.h0 = L.h0; lp.W = L.W; lp.z = L.z; lp.x = L.x;
-  lp.lam = L.lam; lp.excl = L.excl; lp.status = L.status;
-  lp.t = 1;
-  HIP_TRY(launch_ls_update(lp, 1, st));
-  const int switch_t = opt->switch_t > 0 ? opt->switch_t : (F ? 2 + (5 * g.logN) / 6 : 1 + g.logN);
-  for (int t = 2; t <= K; ++t) {
-    const bool fast = opt->corr_method == FCMP_CORR_FAST ||
-                      (opt->corr_method == FCMP_CORR_ADAPTIVE && t <= switch_t);
-    int npart;
-    if (fast) {
-      FParams fp{};
-      fp.N = N; fp.logN = g.logN; fp.fourier = F; fp.c_kind = pk;
-      fp.h0 = L.h0; fp.c = L.cp; fp.lam = L.lam; fp.x = L.x; fp.ntaps = t - 1;
-      fp.h = nullptr; fp.partial = L.com.partial; fp.excl = L.excl; fp.status = L.status;
-      HIP_TRY(launch_fastcorr(fp, 1, &npart, st));
-    } else {
-      RParams rp{};
-      rp.N = N; rp.logN = g.logN; rp.twS = g.twS; rp.fourier = F; rp.M = M;
-      rp.ent_k = L.com.ent_k; rp.y = yent; rp.r = L.r; rp.r_kind = pk;
-      rp.lam = L.lam; rp.x = L.x; rp.ntaps = t - 1;
-      rp.tw_lo = L.com.tw64; rp.tw_hi = L.com.tw64 + ((size_t)1 << g.twS);
-      rp.status = L.status;
-      HIP_TRY(launch_residual(rp, 1, st));
-      XDst d;
-      d.partial = L.com.partial; d.excl = L.excl;
-      d.scale = 1.0 / std::sqrt((double)N);
-      HIP_TRY(run_transform(pk, +1, g, tw_for(pk, g, L.com), en, XSrc{IN_SPARSE, pk, L.r}, d,
-                            L.com.tmp, L.status, st));
-      npart = transform_partials(pk, g);
-    }
-    lp.t = t;
-    lp.npart = npart;
-    HIP_TRY(launch_ls_update(lp, 1, st));
-  }
-  HIP_TRY(launch_finalize(F, L.status, L.lam, L.x, K, support_dev, x_dev, st));
-  return FCMP_OK;
-}
-
-int fill_stats(const OmpLayout& L, fcmp_stats* stats, hipEvent_t e0, hipEvent_t e1,
-               hipStream_t st) {
-  HIP_TRY(hipStreamSynchronize(st));
-  Status s;
-  HIP_TRY(hipMemcpy(&s, L.status, sizeof(Status), hipMemcpyDeviceToHost));
-  float ms = 0.f;
-  if (e0 && e1) HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  stats->iterations = s.iterations;
-  stats->status = s.numeric ? FCMP_E_NUMERIC : FCMP_OK;
-  const double r2 = s.ynorm2 - s.znorm2;
-  stats->res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
-  stats->ms_total = ms;
-  return stats->status;
-}
-
 }  // namespace
 
 extern "C" {
@@ -222,45 +92,77 @@ const char* fcmp_status_str(int s) {
 const char* fcmp_last_error(void) { return fcmp::last_error(); }
 
 int fcmp_query_workspace(const fcmp_problem* prob, const fcmp_options* opt, size_t* bytes) {
-  int rc = validate_problem(prob, true);
-  if (rc) return rc;
-  if ((rc = validate_options(prob, opt))) return rc;
   if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
-  if (opt->algorithm != FCMP_OMP) return set_error(FCMP_E_INVALID, "algorithm not available");
-  *bytes = omp_layout(prob, opt, nullptr).total;
+  fcmp_plan P;
+  int rc = plan_init(P, 1, prob, opt);
+  if (rc) return rc;
+  *bytes = P.total;
   return FCMP_OK;
 }
 
 int fcmp_solve(const fcmp_problem* prob, const fcmp_options* opt, const void* y_dev,
                void* ws_dev, size_t ws_bytes, int32_t* support_dev, void* x_dev,
                fcmp_stats* stats, void* hip_stream) {
-  int rc = validate_problem(prob, true);
+  fcmp_plan P;
+  int rc = plan_init(P, 1, prob, opt);
   if (rc) return rc;
-  if ((rc = validate_options(prob, opt))) return rc;
   if (!y_dev || !ws_dev || !support_dev || !x_dev)
     return set_error(FCMP_E_INVALID, "NULL device pointer");
-  if (opt->algorithm != FCMP_OMP) return set_error(FCMP_E_INVALID, "algorithm not available");
-  const OmpLayout need = omp_layout(prob, opt, nullptr);
-  if (ws_bytes < need.total) return set_error(FCMP_E_WORKSPACE, "workspace too small");
+  if (ws_bytes < P.total) return set_error(FCMP_E_WORKSPACE, "workspace too small");
+  plan_layout(P, (char*)ws_dev);
   hipStream_t st = (hipStream_t)hip_stream;
-  const OmpLayout L = omp_layout(prob, opt, ws_dev);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (stats) {
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
-  }
-  rc = omp_enqueue(prob, opt, y_dev, L, support_dev, x_dev, st);
-  if (stats) {
-    if (rc == FCMP_OK) {
-      HIP_TRY(hipEventRecord(e1, st));
-      rc = fill_stats(L, stats, e0, e1, st);
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-  }
-  return rc;
+  if ((rc = plan_build(P, prob, st))) return rc;
+  const void* yp[1] = {y_dev};
+  int32_t* sp[1] = {support_dev};
+  void* xp[1] = {x_dev};
+  return plan_solve(P, nullptr, yp, sp, xp, stats, st);
 }
+
+int fcmp_plan_query_workspace(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
+                              size_t* bytes) {
+  if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
+  fcmp_plan P;
+  int rc = plan_init(P, n, probs, opt);
+  if (rc) return rc;
+  *bytes = P.total;
+  return FCMP_OK;
+}
+
+int fcmp_plan_create(fcmp_plan** out, int64_t n, const fcmp_problem* probs,
+                     const fcmp_options* opt, void* ws_dev, size_t ws_bytes, void* hip_stream) {
+  if (!out) return set_error(FCMP_E_INVALID, "out is NULL");
+  *out = nullptr;
+  fcmp_plan* P = new fcmp_plan();
+  int rc = plan_init(*P, n, probs, opt);
+  if (rc == FCMP_OK && !ws_dev) rc = set_error(FCMP_E_INVALID, "workspace is NULL");
+  if (rc == FCMP_OK && ws_bytes < P->total)
+    rc = set_error(FCMP_E_WORKSPACE, "workspace too small");
+  if (rc == FCMP_OK) {
+    plan_layout(*P, (char*)ws_dev);
+    rc = plan_build(*P, probs, (hipStream_t)hip_stream);
+  }
+  if (rc) {
+    delete P;
+    return rc;
+  }
+  *out = P;
+  return FCMP_OK;
+}
+
+int fcmp_plan_solve(fcmp_plan* plan, const fcmp_options* opt, const void* const* y_dev,
+                    int32_t* const* support_dev, void* const* x_dev, fcmp_stats* stats,
+                    void* hip_stream) {
+  if (!plan) return set_error(FCMP_E_INVALID, "plan is NULL");
+  return plan_solve(*plan, opt, y_dev, support_dev, x_dev, stats, (hipStream_t)hip_stream);
+}
+
+int fcmp_plan_destroy(fcmp_plan* plan) {
+  delete plan;
+  return FCMP_OK;
+}
+
+int fcmp_profile_enable(int enable) { return profile_enable(enable); }
+int fcmp_profile_read(fcmp_profile* out, int reset) { return profile_read(out, reset); }
 
 // ---------------------------------------------------------------- steps
 static void carve_kv(Carver& cv, const Geo& g, int M, Common& c) { carve_common(cv, g, M, c); }
@@ -447,19 +349,79 @@ int fcmp_measure(const fcmp_problem* prob, const void* x_dev, const void* noise_
   return FCMP_OK;
 }
 
+static int batch_groups(int64_t n, const fcmp_problem* probs,
+                        std::vector<std::vector<int64_t>>& groups) {
+  if (n < 1 || !probs) return set_error(FCMP_E_INVALID, "empty batch");
+  std::map<std::tuple<int, int64_t, int64_t, int64_t>, size_t> idx;
+  for (int64_t b = 0; b < n; ++b) {
+    const auto key = std::make_tuple(probs[b].matrix_class, probs[b].N, probs[b].M, probs[b].K);
+    auto it = idx.find(key);
+    if (it == idx.end()) {
+      idx[key] = groups.size();
+      groups.push_back({b});
+    } else {
+      groups[it->second].push_back(b);
+    }
+  }
+  return FCMP_OK;
+}
+
 int fcmp_batch_query_workspace(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
                                size_t* bytes) {
-  (void)n; (void)probs; (void)opt; (void)bytes;
-  return set_error(FCMP_E_INVALID, "batch solve not available");
+  if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
+  std::vector<std::vector<int64_t>> groups;
+  int rc = batch_groups(n, probs, groups);
+  if (rc) return rc;
+  size_t need = 0;
+  for (const auto& gidx : groups) {
+    std::vector<fcmp_problem> sub;
+    for (int64_t b : gidx) sub.push_back(probs[b]);
+    fcmp_plan P;
+    if ((rc = plan_init(P, (int64_t)sub.size(), sub.data(), opt))) return rc;
+    need = std::max(need, P.total);
+  }
+  *bytes = need;
+  return FCMP_OK;
 }
 
 int fcmp_batch_solve(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
                      const void* const* y_dev, void* ws_dev, size_t ws_bytes,
                      int32_t* const* support_dev, void* const* x_dev, fcmp_stats* stats,
                      void* hip_stream) {
-  (void)n; (void)probs; (void)opt; (void)y_dev; (void)ws_dev; (void)ws_bytes;
-  (void)support_dev; (void)x_dev; (void)stats; (void)hip_stream;
-  return set_error(FCMP_E_INVALID, "batch solve not available");
+  size_t need = 0;
+  int rc = fcmp_batch_query_workspace(n, probs, opt, &need);
+  if (rc) return rc;
+  if (!ws_dev) return set_error(FCMP_E_INVALID, "workspace is NULL");
+  if (ws_bytes < need) return set_error(FCMP_E_WORKSPACE, "workspace too small");
+  if (!y_dev || !support_dev || !x_dev) return set_error(FCMP_E_INVALID, "NULL pointer array");
+  std::vector<std::vector<int64_t>> groups;
+  batch_groups(n, probs, groups);
+  hipStream_t st = (hipStream_t)hip_stream;
+  int worst = FCMP_OK;
+  // groups share the workspace one after another (each plan build synchronises)
+  for (const auto& gidx : groups) {
+    std::vector<fcmp_problem> sub;
+    std::vector<const void*> ys;
+    std::vector<int32_t*> ss;
+    std::vector<void*> xs;
+    std::vector<fcmp_stats> sts(gidx.size());
+    for (int64_t b : gidx) {
+      sub.push_back(probs[b]);
+      ys.push_back(y_dev[b]);
+      ss.push_back(support_dev[b]);
+      xs.push_back(x_dev[b]);
+    }
+    fcmp_plan P;
+    if ((rc = plan_init(P, (int64_t)sub.size(), sub.data(), opt))) return rc;
+    plan_layout(P, (char*)ws_dev);
+    if ((rc = plan_build(P, sub.data(), st))) return rc;
+    rc = plan_solve(P, nullptr, ys.data(), ss.data(), xs.data(), sts.data(), st);
+    if (rc && rc != FCMP_E_NUMERIC) return rc;
+    if (rc) worst = rc;
+    if (stats)
+      for (size_t i = 0; i < gidx.size(); ++i) stats[gidx[i]] = sts[i];
+  }
+  return worst;
 }
 
 }  // extern "C"

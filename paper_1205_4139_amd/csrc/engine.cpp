@@ -117,6 +117,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
     p.scale = out.scale;
     p.partial = out.partial; p.inst_part = isp;
     p.nthreads = pick_threads(g.N);
+    p.role = 0;
     return launch_xform(vk, fft, p, 1, ninst, st);
   }
   const int N1 = 1 << g.n1, N2 = 1 << g.n2;
@@ -134,6 +135,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   a.scale = 1.0;
   a.partial = nullptr; a.excl = nullptr;
   a.nthreads = pick_threads(a.L * a.B);
+  a.role = 1;
   hipError_t e = launch_xform(vk, fft, a, N1 / g.B1, ninst, st);
   if (e != hipSuccess) return e;
   // pass 2: N2 sequences (rows j2) of length N1 over k1
@@ -151,6 +153,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   b.scale = out.scale;
   b.partial = out.partial; b.inst_part = isp;
   b.nthreads = pick_threads(b.L * b.B);
+  b.role = 2;
   return launch_xform(vk, fft, b, N2 / g.B2, ninst, st);
 }
 
@@ -188,6 +191,7 @@ int validate_options(const fcmp_problem* p, const fcmp_options* o) {
   if (o->max_iter < 0) return set_error(FCMP_E_INVALID, "max_iter must be >= 0");
   if (o->switch_t < 0) return set_error(FCMP_E_INVALID, "switch_t must be >= 0");
   if (o->res_tol != 0.0) return set_error(FCMP_E_INVALID, "res_tol is reserved and must be 0");
+  if (o->flags & ~FCMP_FLAG_RECOMPUTE_KERNEL) return set_error(FCMP_E_INVALID, "unknown flags");
   if (o->algorithm == FCMP_OMP && p->K > 4096)
     return set_error(FCMP_E_INVALID, "OMP supports K <= 4096");
   if (o->algorithm == FCMP_SP && 2 * p->K > p->M)

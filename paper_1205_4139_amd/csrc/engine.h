@@ -68,6 +68,24 @@ struct Carver {
   size_t total() const { return (off + 255) & ~(size_t)255; }
 };
 
+// RAII phase timer: records hipEvents around a launch sequence when profiling
+// is enabled (fcmp_profile_enable); no-op otherwise.
+class ProfScope {
+ public:
+  ProfScope(int phase, hipStream_t st);
+  ~ProfScope();
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
+
+ private:
+  int phase_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr;
+};
+bool prof_enabled();
+int profile_enable(int enable);
+int profile_read(fcmp_profile* out, int reset);
+
 int validate_problem(const fcmp_problem* p, bool need_k);
 int validate_options(const fcmp_problem* p, const fcmp_options* o);
 

@@ -47,6 +47,7 @@ struct XParams {
   // per-instance strides (blockIdx.y), in elements of each array
   int64_t inst_in, inst_ent, inst_goff, inst_out, inst_out2, inst_part, inst_excl;
   int nthreads;
+  int role;                // 0 single workgroup, 1 pass 1, 2 pass 2 (profiler name only)
 };
 
 // vk: VKind of the transform arithmetic; fft: Fourier (else Hadamard)
@@ -126,6 +127,12 @@ hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam
 hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st);
 hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier,
                               int64_t inst_y, int ninst, hipStream_t st);
+hipError_t launch_gather_ptr(int vk, const void* const* ptrs, const int32_t* idx, void* dst,
+                             int64_t n, int64_t inst_idx, int64_t inst_dst, int ninst,
+                             hipStream_t st);
+hipError_t launch_finalize_ptr(int fourier, const Status* status, const int32_t* lam,
+                               const void* x, int K, int64_t inst_lam, int64_t inst_x,
+                               int32_t* const* sup, void* const* xo, int ninst, hipStream_t st);
 hipError_t launch_noise(int fourier, const void* clean, const void* noise, double snr_db,
                         void* y, int M, hipStream_t st);
 

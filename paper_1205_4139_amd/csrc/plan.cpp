@@ -1,0 +1,269 @@
+// Plan construction and the lockstep OMP solve (Algorithm 1.1 with either
+// correlation method), n instances of one shape per launch.
+#include "plan.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace fcmp {
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return set_error(FCMP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+static int64_t pad64(int64_t v) { return (v + 63) & ~int64_t(63); }
+
+int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt) {
+  if (n < 1) return set_error(FCMP_E_INVALID, "n must be >= 1");
+  if (!probs) return set_error(FCMP_E_INVALID, "problems is NULL");
+  for (int64_t b = 0; b < n; ++b) {
+    int rc = validate_problem(&probs[b], true);
+    if (rc) return rc;
+    if (probs[b].matrix_class != probs[0].matrix_class || probs[b].N != probs[0].N ||
+        probs[b].M != probs[0].M || probs[b].K != probs[0].K)
+      return set_error(FCMP_E_INVALID, "plan problems must share class, N, M and K");
+  }
+  int rc = validate_options(&probs[0], opt);
+  if (rc) return rc;
+  if (opt->algorithm != FCMP_OMP) return set_error(FCMP_E_INVALID, "algorithm not available");
+  P.n = n;
+  P.shape = probs[0];
+  P.shape.omega = nullptr;
+  P.opt = *opt;
+  const bool F = P.shape.matrix_class == FCMP_FOURIER;
+  P.g = make_geo(F, (int)P.shape.N);
+  P.wk = F ? V_C128 : V_F64;
+  P.pk = opt->corr_precision == FCMP_FP32 ? (F ? V_C64 : V_F32) : P.wk;
+  const int64_t N = P.shape.N, M = P.shape.M, K = P.shape.K;
+  P.sM = pad64(M);
+  P.sN = pad64(N);
+  P.sK = pad64(K);
+  P.sW = pad64(K * (K + 1) / 2);
+  P.sG = pad64(P.g.ngroups + 1);
+  P.npart = std::max(std::max(transform_partials(P.wk, P.g), transform_partials(P.pk, P.g)),
+                     fastcorr_groups((int)N));
+  P.sP = pad64(P.npart);
+  P.sE = pad64((N + 31) / 32);
+  plan_layout(P, nullptr);
+  return FCMP_OK;
+}
+
+void plan_layout(fcmp_plan& P, char* base) {
+  Carver cv;
+  cv.base = base;
+  const int64_t n = P.n;
+  const size_t ntw = ((size_t)1 << P.g.twS) + ((size_t)P.g.N >> P.g.twS);
+  const size_t wb = vbytes(P.wk), pb = vbytes(P.pk);
+  P.tw64 = cv.take<double2>(ntw);
+  P.tw32 = cv.take<float2>(ntw);
+  P.ent_k = cv.take<int32_t>(n * P.sM);
+  P.perm = cv.take<int32_t>(n * P.sM);
+  P.goff = cv.take<int32_t>(n * P.sG);
+  P.c64 = cv.take_bytes(n * P.sN * wb);
+  P.cp = P.pk == P.wk ? P.c64 : cv.take_bytes(n * P.sN * pb);
+  P.y_ent = cv.take_bytes(n * P.sM * wb);
+  P.r = cv.take_bytes(n * P.sM * pb);
+  P.h0 = cv.take_bytes(n * P.sN * wb);
+  P.tmp = cv.take_bytes(n * P.sN * wb);
+  P.partial = cv.take<Sel>(n * P.sP);
+  P.lam = cv.take<int32_t>(n * P.sK);
+  P.excl = cv.take<uint32_t>(n * P.sE);
+  P.x = cv.take_bytes(n * P.sK * wb);
+  P.z = cv.take_bytes(n * P.sK * wb);
+  P.W = cv.take_bytes(n * P.sW * wb);
+  P.status = cv.take<Status>(n);
+  P.dptrs = cv.take<void*>(3 * n);
+  P.total = cv.total();
+}
+
+static TwDev tw_for(const fcmp_plan& P, int vk) {
+  const size_t nlo = (size_t)1 << P.g.twS;
+  if (vk == V_C64) return TwDev{P.tw32, P.tw32 + nlo};
+  return TwDev{P.tw64, P.tw64 + nlo};
+}
+
+int plan_kernel_vector(fcmp_plan& P, hipStream_t st) {
+  ProfScope ps(FCMP_PHASE_KERNEL, st);
+  XDst d;
+  d.out = P.c64; d.kind = P.wk;
+  if (P.cp != P.c64) { d.out2 = P.cp; d.kind2 = P.pk; }
+  d.scale = 1.0 / (double)P.shape.N;
+  HIP_TRY(run_transform(P.wk, +1, P.g, tw_for(P, P.wk),
+                        EntDev{P.ent_k, P.goff, (int)P.shape.M}, XSrc{IN_SPARSE_ONES, P.wk, nullptr},
+                        d, P.tmp, nullptr, st, (int)P.n, P.sN, P.sM, 0, 0, P.sG));
+  return FCMP_OK;
+}
+
+int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
+  const int64_t n = P.n, M = P.shape.M;
+  std::vector<int32_t> ent((size_t)(n * P.sM), 0), perm((size_t)(n * P.sM), 0),
+      goff((size_t)(n * P.sG), 0);
+  HostTables t;
+  for (int64_t b = 0; b < n; ++b) {
+    build_tables(P.g, probs[b].omega, (int)M, t);
+    std::memcpy(&ent[b * P.sM], t.ent_k.data(), M * 4);
+    std::memcpy(&perm[b * P.sM], t.perm.data(), M * 4);
+    std::memcpy(&goff[b * P.sG], t.goff.data(), t.goff.size() * 4);
+  }
+  HIP_TRY(hipMemcpyAsync(P.tw64, t.tw64.data(), t.tw64.size() * sizeof(double2),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.tw32, t.tw32.data(), t.tw32.size() * sizeof(float2),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.ent_k, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.goff, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, st));
+  int rc = plan_kernel_vector(P, st);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(st));
+  P.last_ptrs.clear();
+  return FCMP_OK;
+}
+
+static int upload_ptrs(fcmp_plan& P, const void* const* y, int32_t* const* sup, void* const* x,
+                       hipStream_t st) {
+  std::vector<const void*> want((size_t)(3 * P.n));
+  for (int64_t b = 0; b < P.n; ++b) {
+    if (!y[b] || !sup[b] || !x[b]) return set_error(FCMP_E_INVALID, "NULL device pointer");
+    want[b] = y[b];
+    want[P.n + b] = sup[b];
+    want[2 * P.n + b] = x[b];
+  }
+  if (want == P.last_ptrs) return FCMP_OK;
+  HIP_TRY(hipMemcpyAsync(P.dptrs, want.data(), want.size() * sizeof(void*),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));   // the host array is the caller's
+  P.last_ptrs = want;
+  return FCMP_OK;
+}
+
+int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_t* const* sup,
+               void* const* xo, fcmp_stats* stats, hipStream_t st) {
+  fcmp_options opt = P.opt;
+  if (o) {
+    int rc = validate_options(&P.shape, o);
+    if (rc) return rc;
+    if (o->algorithm != P.opt.algorithm || o->corr_precision != P.opt.corr_precision)
+      return set_error(FCMP_E_INVALID, "options differ from the plan's algorithm/precision");
+    opt = *o;
+  }
+  if (!y || !sup || !xo) return set_error(FCMP_E_INVALID, "NULL pointer array");
+  int rc = upload_ptrs(P, y, sup, xo, st);
+  if (rc) return rc;
+  const bool F = P.shape.matrix_class == FCMP_FOURIER;
+  const int n = (int)P.n;
+  const int N = (int)P.shape.N, M = (int)P.shape.M, K = (int)P.shape.K;
+  const Geo& g = P.g;
+  const EntDev en{P.ent_k, P.goff, M};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  if (opt.flags & FCMP_FLAG_RECOMPUTE_KERNEL) {
+    if ((rc = plan_kernel_vector(P, st))) return rc;
+  }
+  {
+    ProfScope ps(FCMP_PHASE_OTHER, st);
+    HIP_TRY(launch_fill_u32(P.excl, 0u, P.n * P.sE, st));
+    HIP_TRY(launch_gather_ptr(P.wk, (const void* const*)P.dptrs, P.perm, P.y_ent, M, P.sM, P.sM,
+                              n, st));
+    HIP_TRY(launch_init_status(P.status, P.y_ent, M, F, P.sM, n, st));
+  }
+  const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
+  {
+    // A2: h_0 = Phi^H y in FP64 with the first identification fused
+    ProfScope ps(FCMP_PHASE_H0, st);
+    XDst d;
+    d.out = P.h0; d.kind = P.wk;
+    d.partial = P.partial; d.excl = P.excl;
+    d.scale = inv_sqrt_n;
+    HIP_TRY(run_transform(P.wk, +1, g, tw_for(P, P.wk), en, XSrc{IN_SPARSE, P.wk, P.y_ent}, d,
+                          P.tmp, nullptr, st, n, P.sN, P.sM, P.sP, P.sE, P.sG));
+  }
+  LParams lp{};
+  lp.N = N; lp.fourier = F;
+  lp.partial = P.partial; lp.npart = transform_partials(P.wk, g);
+  lp.c64 = P.c64; lp.h0 = P.h0; lp.W = P.W; lp.z = P.z; lp.x = P.x;
+  lp.lam = P.lam; lp.excl = P.excl; lp.status = P.status;
+  lp.inst_part = P.sP; lp.inst_c = P.sN; lp.inst_h0 = P.sN; lp.inst_W = P.sW;
+  lp.inst_z = P.sK; lp.inst_x = P.sK; lp.inst_lam = P.sK; lp.inst_excl = P.sE;
+  lp.t = 1;
+  {
+    ProfScope ps(FCMP_PHASE_LS, st);
+    HIP_TRY(launch_ls_update(lp, n, st));
+  }
+  const int switch_t =
+      opt.switch_t > 0 ? opt.switch_t : (F ? 2 + (5 * g.logN) / 6 : 1 + g.logN);
+  for (int t = 2; t <= K; ++t) {
+    const bool fast = opt.corr_method == FCMP_CORR_FAST ||
+                      (opt.corr_method == FCMP_CORR_ADAPTIVE && t <= switch_t);
+    int npart;
+    if (fast) {
+      ProfScope ps(FCMP_PHASE_FAST, st);
+      FParams fp{};
+      fp.N = N; fp.logN = g.logN; fp.fourier = F; fp.c_kind = P.pk;
+      fp.h0 = P.h0; fp.c = P.cp; fp.lam = P.lam; fp.x = P.x; fp.ntaps = t - 1;
+      fp.h = nullptr; fp.partial = P.partial; fp.excl = P.excl; fp.status = P.status;
+      fp.inst_h0 = P.sN; fp.inst_c = P.sN; fp.inst_lam = P.sK; fp.inst_x = P.sK;
+      fp.inst_h = 0; fp.inst_part = P.sP; fp.inst_excl = P.sE;
+      HIP_TRY(launch_fastcorr(fp, n, &npart, st));
+    } else {
+      {
+        ProfScope ps(FCMP_PHASE_RESID, st);
+        RParams rp{};
+        rp.N = N; rp.logN = g.logN; rp.twS = g.twS; rp.fourier = F; rp.M = M;
+        rp.ent_k = P.ent_k; rp.y = P.y_ent; rp.r = P.r; rp.r_kind = P.pk;
+        rp.lam = P.lam; rp.x = P.x; rp.ntaps = t - 1;
+        rp.tw_lo = P.tw64; rp.tw_hi = P.tw64 + ((size_t)1 << g.twS);
+        rp.status = P.status;
+        rp.inst_ent = P.sM; rp.inst_y = P.sM; rp.inst_r = P.sM; rp.inst_lam = P.sK;
+        rp.inst_x = P.sK;
+        HIP_TRY(launch_residual(rp, n, st));
+      }
+      ProfScope ps(FCMP_PHASE_CORR, st);
+      XDst d;
+      d.partial = P.partial; d.excl = P.excl;
+      d.scale = inv_sqrt_n;
+      HIP_TRY(run_transform(P.pk, +1, g, tw_for(P, P.pk), en, XSrc{IN_SPARSE, P.pk, P.r}, d,
+                            P.tmp, P.status, st, n, P.sN, P.sM, P.sP, P.sE, P.sG));
+      npart = transform_partials(P.pk, g);
+    }
+    lp.t = t;
+    lp.npart = npart;
+    ProfScope ps(FCMP_PHASE_LS, st);
+    HIP_TRY(launch_ls_update(lp, n, st));
+  }
+  {
+    ProfScope ps(FCMP_PHASE_OTHER, st);
+    HIP_TRY(launch_finalize_ptr(F, P.status, P.lam, P.x, K, P.sK, P.sK,
+                                (int32_t* const*)(P.dptrs + P.n), (void* const*)(P.dptrs + 2 * P.n),
+                                n, st));
+  }
+  if (stats) {
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    std::vector<Status> hs((size_t)n);
+    HIP_TRY(hipMemcpy(hs.data(), P.status, n * sizeof(Status), hipMemcpyDeviceToHost));
+    int worst = FCMP_OK;
+    for (int b = 0; b < n; ++b) {
+      stats[b].iterations = hs[b].iterations;
+      stats[b].status = hs[b].numeric ? FCMP_E_NUMERIC : FCMP_OK;
+      const double r2 = hs[b].ynorm2 - hs[b].znorm2;
+      stats[b].res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
+      stats[b].ms_total = ms;
+      if (stats[b].status != FCMP_OK) worst = stats[b].status;
+    }
+    if (worst != FCMP_OK) return set_error(worst, "Cholesky breakdown in at least one instance");
+  }
+  return FCMP_OK;
+}
+
+}  // namespace fcmp

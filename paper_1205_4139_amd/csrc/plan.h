@@ -1,0 +1,52 @@
+// Plans: Omega-derived tables, the kernel vector and per-solve buffers for n
+// problems of one shape, solved in lockstep.
+#pragma once
+#include <vector>
+
+#include "engine.h"
+
+struct fcmp_plan {
+  int64_t n = 0;
+  fcmp_problem shape{};        // class, N, M, K (omega not kept)
+  fcmp_options opt{};          // algorithm and precision fixed at creation
+  fcmp::Geo g;
+  int wk = 0, pk = 0;          // wide and correlation-precision value kinds
+  // per-instance strides in elements
+  int64_t sM = 0, sN = 0, sK = 0, sW = 0, sG = 0, sP = 0, sE = 0;
+  int npart = 1;
+  // shared
+  double2* tw64 = nullptr;
+  float2* tw32 = nullptr;
+  // per instance (n * stride)
+  int32_t* ent_k = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* goff = nullptr;
+  void* c64 = nullptr;
+  void* cp = nullptr;
+  void* y_ent = nullptr;
+  void* r = nullptr;
+  void* h0 = nullptr;
+  void* tmp = nullptr;
+  fcmp::Sel* partial = nullptr;
+  int32_t* lam = nullptr;
+  uint32_t* excl = nullptr;
+  void* x = nullptr;
+  void* z = nullptr;
+  void* W = nullptr;
+  fcmp::Status* status = nullptr;
+  void** dptrs = nullptr;      // 3n device pointers: y, support, x
+  std::vector<const void*> last_ptrs;
+  size_t total = 0;
+};
+
+namespace fcmp {
+
+// Lays out the plan's buffers from base (nullptr: sizes only).
+void plan_layout(fcmp_plan& P, char* base);
+int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt);
+int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st);
+int plan_solve(fcmp_plan& P, const fcmp_options* opt, const void* const* y,
+               int32_t* const* sup, void* const* x, fcmp_stats* stats, hipStream_t st);
+int plan_kernel_vector(fcmp_plan& P, hipStream_t st);
+
+}  // namespace fcmp

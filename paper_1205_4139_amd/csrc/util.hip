@@ -135,4 +135,57 @@ hipError_t launch_noise(int fourier, const void* clean, const void* noise, doubl
   return hipGetLastError();
 }
 
+// dst[b][p] = src_b[idx[b][p]] with src_b = ptrs[b] (per-instance caller buffers)
+template <class T>
+__global__ void gather_ptr_kernel(const T* const* ptrs, const int32_t* idx, T* dst, int64_t n,
+                                  int64_t ii, int64_t id) {
+  const int inst = blockIdx.y;
+  const T* src = ptrs[inst];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[inst * id + e] = src[idx[inst * ii + e]];
+}
+
+hipError_t launch_gather_ptr(int vk, const void* const* ptrs, const int32_t* idx, void* dst,
+                             int64_t n, int64_t ii, int64_t id, int ninst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int64_t groups = (n + 255) / 256;
+  if (groups > 1024) groups = 1024;
+  dim3 grid((unsigned)groups, ninst);
+  if (vbytes(vk) == 16)
+    hipLaunchKernelGGL(gather_ptr_kernel<double2>, grid, dim3(256), 0, st,
+                       (const double2* const*)ptrs, idx, (double2*)dst, n, ii, id);
+  else
+    hipLaunchKernelGGL(gather_ptr_kernel<double>, grid, dim3(256), 0, st,
+                       (const double* const*)ptrs, idx, (double*)dst, n, ii, id);
+  return hipGetLastError();
+}
+
+template <class Wd>
+__global__ void finalize_ptr_kernel(const Status* status, const int32_t* lam, const Wd* x, int K,
+                                    int64_t il, int64_t ix, int32_t* const* sup, Wd* const* xo) {
+  const int inst = blockIdx.y;
+  const int it = status[inst].iterations;
+  int32_t* s = sup[inst];
+  Wd* xd = xo[inst];
+  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < K; i += blockDim.x * gridDim.x) {
+    const bool ok = i < it;
+    s[i] = ok ? lam[inst * il + i] : -1;
+    xd[i] = ok ? x[inst * ix + i] : vzero(Wd());
+  }
+}
+
+hipError_t launch_finalize_ptr(int fourier, const Status* status, const int32_t* lam,
+                               const void* x, int K, int64_t il, int64_t ix,
+                               int32_t* const* sup, void* const* xo, int ninst, hipStream_t st) {
+  dim3 grid((K + 255) / 256, ninst);
+  if (fourier)
+    hipLaunchKernelGGL(finalize_ptr_kernel<double2>, grid, dim3(256), 0, st, status, lam,
+                       (const double2*)x, K, il, ix, sup, (double2* const*)xo);
+  else
+    hipLaunchKernelGGL(finalize_ptr_kernel<double>, grid, dim3(256), 0, st, status, lam,
+                       (const double*)x, K, il, ix, sup, (double* const*)xo);
+  return hipGetLastError();
+}
+
 }  // namespace fcmp

@@ -171,7 +171,9 @@ __device__ void lds_fft(V* t, int L, int logL, int B, int logB, const V* lo, con
   }
 }
 
-template <class V, bool FFT>
+// ROLE only names the launch for profilers: 0 one workgroup per transform,
+// 1 first pass (columns), 2 second pass (rows).
+template <class V, bool FFT, int ROLE>
 __global__ void __launch_bounds__(1024) xform_kernel(XParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int inst = blockIdx.y;
@@ -280,9 +282,9 @@ size_t xform_lds_bytes(int vk, bool fft, int L, int B, int N, int twS) {
   return bytes;
 }
 
-template <class V, bool FFT>
-static hipError_t launch_t(const XParams& p, int groups, int ninst, size_t lds, hipStream_t st) {
-  auto kfn = xform_kernel<V, FFT>;
+template <class V, bool FFT, int ROLE>
+static hipError_t launch_r(const XParams& p, int groups, int ninst, size_t lds, hipStream_t st) {
+  auto kfn = xform_kernel<V, FFT, ROLE>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void*)kfn,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -290,6 +292,13 @@ static hipError_t launch_t(const XParams& p, int groups, int ninst, size_t lds, 
   }
   hipLaunchKernelGGL(kfn, dim3(groups, ninst), dim3(p.nthreads), lds, st, p);
   return hipGetLastError();
+}
+
+template <class V, bool FFT>
+static hipError_t launch_t(const XParams& p, int groups, int ninst, size_t lds, hipStream_t st) {
+  if (p.role == 1) return launch_r<V, FFT, 1>(p, groups, ninst, lds, st);
+  if (p.role == 2) return launch_r<V, FFT, 2>(p, groups, ninst, lds, st);
+  return launch_r<V, FFT, 0>(p, groups, ninst, lds, st);
 }
 
 hipError_t launch_xform(int vk, bool fft, const XParams& p, int groups, int ninst,

@@ -1,0 +1,88 @@
+"""Lockstep plans and mixed batches: every instance must match the oracle on
+certified instances, and each result must be bit-identical to the same
+instance solved alone."""
+import numpy as np
+import pytest
+
+import instancegen
+import oracle
+from oracle import certify
+from tests.gpu_util import lib, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fc():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return lib()
+
+
+def _insts(cls, N, M, K, law, snr, n, base):
+    out = []
+    for i in range(n):
+        inst = instancegen.draw_instance(cls, N, M, K, law, snr, base + i)
+        y = oracle.problem.instance_measure(inst, tier="transform")
+        out.append((inst, y))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["conventional", "fast", "adaptive"])
+@pytest.mark.parametrize("shape", [("H", 4096, 1000, 37, "gauss", 40.0),
+                                   ("F", 16384, 4096, 40, "cgauss", 30.0)],
+                         ids=["H4096", "F16384"])
+def test_plan_lockstep_matches_alone_and_oracle(fc, shape, method, precision):
+    import torch
+    cls, N, M, K, law, snr = shape
+    data = _insts(cls, N, M, K, law, snr, 5, 8100)
+    plan = fc.Plan(cls, N, M, K, [d[0].omega for d in data], precision=precision, method=method)
+    ys = torch.stack([to_dev(d[1]) for d in data])
+    sup, x, stats = plan.solve(ys, method=method, stats=True)
+    sup = to_np(sup)
+    x = to_np(x)
+    for b, (inst, y) in enumerate(data):
+        alone = fc.solve(cls, N, M, K, inst.omega, to_dev(y), method=method, precision=precision)
+        assert np.array_equal(to_np(alone.support), sup[b])
+        assert np.array_equal(to_np(alone.x), x[b])
+        ref = oracle.omp(oracle.make_operator(cls, N, inst.omega), y, K)
+        if certify.certified(ref, precision):
+            assert list(sup[b]) == list(ref.support)
+            assert np.linalg.norm(x[b] - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+        assert stats[b].iterations == K
+
+
+def test_plan_reuse_and_kernel_recompute(fc):
+    """A plan solves several right-hand sides; recomputing the kernel vector
+    inside the solve gives bit-identical results."""
+    import torch
+    data = _insts("F", 4096, 1024, 20, "cgauss", 30.0, 3, 8200)
+    plan = fc.Plan("F", 4096, 1024, 20, [d[0].omega for d in data], precision="fp32")
+    ys = torch.stack([to_dev(d[1]) for d in data])
+    s1, x1, _ = plan.solve(ys)
+    s1, x1 = to_np(s1).copy(), to_np(x1).copy()
+    s2, x2, _ = plan.solve(ys, flags=fc.FLAG_RECOMPUTE_KERNEL)
+    assert np.array_equal(s1, to_np(s2)) and np.array_equal(x1, to_np(x2))
+    s3, x3, _ = plan.solve(ys * 2.0)
+    assert np.array_equal(s1, to_np(s3))
+    assert np.allclose(to_np(x3), 2 * x1, rtol=1e-12, atol=0)
+
+
+def test_mixed_batch_solve(fc):
+    shapes = [("H", 1024, 256, 16, "gauss", None), ("F", 2048, 512, 20, "cgauss", 30.0),
+              ("H", 1024, 256, 16, "gauss", None), ("F", 65536, 8192, 30, "cgauss", 30.0)]
+    probs, ys, refs = [], [], []
+    for i, (cls, N, M, K, law, snr) in enumerate(shapes):
+        inst = instancegen.draw_instance(cls, N, M, K, law, snr, 8300 + i)
+        y = oracle.problem.instance_measure(inst, tier="transform")
+        probs.append((cls, N, M, K, inst.omega))
+        ys.append(to_dev(y))
+        refs.append(oracle.omp(oracle.make_operator(cls, N, inst.omega), y, K))
+    sups, xs, stats = fc.batch_solve(probs, ys)
+    for i, ref in enumerate(refs):
+        if certify.certified(ref, "fp64"):
+            assert list(to_np(sups[i])) == list(ref.support)
+            assert np.linalg.norm(to_np(xs[i]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+        assert stats[i].iterations == probs[i][3]

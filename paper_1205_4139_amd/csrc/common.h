@@ -140,7 +140,7 @@ struct Status {
   int32_t done;        // 1: stop (all later iteration kernels return at once)
   int32_t numeric;     // 1: Cholesky breakdown
   int32_t iterations;  // selections made (OMP) / outer iterations (SP, CoSaMP)
-  int32_t pad;
+  int32_t cur_j;       // column picked by the current iteration
   double  znorm2;      // ||z||^2 = ||y||^2 - ||r||^2
   double  ynorm2;      // ||y||^2
   double  last_key;    // |h|^2 of the last pick

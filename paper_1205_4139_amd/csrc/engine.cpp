@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace fcmp {
@@ -31,11 +32,13 @@ Geo make_geo(bool fourier, int N) {
   g.twS = g.logN / 2;
   g.n2 = g.logN / 2;
   g.n1 = g.logN - g.n2;
-  const int tile = 4096;
+  const int tile = tune().tile;
   g.B1 = std::min(1 << g.n1, std::max(1, tile >> g.n2));
   g.B2 = std::min(1 << g.n2, std::max(1, tile >> g.n1));
   g.grouped = !single_ok(fourier ? V_C128 : V_F64, N);
   g.ngroups = g.grouped ? (1 << g.n1) / g.B1 : 1;
+  g.ngroups2 = g.grouped ? (1 << g.n2) / g.B2 : 1;
+  g.same_out = !g.grouped || (fourier && g.n1 == g.n2 && g.B1 == g.B2);
   return g;
 }
 
@@ -65,6 +68,33 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
       t.ent_k[p] = omega[m];
     }
   }
+  // rows grouped by the pass-2 workgroup that produces them (Fourier output
+  // j = j2 + N2 j1, Hadamard output j = j1 + N1 j2); pos1 maps back to the
+  // pass-1 entry order
+  if (!g.same_out) {
+    const int logB2 = ilog2(g.B2);
+    const int mask2 = (1 << g.n2) - 1;
+    std::vector<int32_t> inv(M);
+    for (int p = 0; p < M; ++p) inv[t.perm[p]] = p;
+    auto grp2 = [&](int k) {
+      return g.fourier ? ((k & mask2) >> logB2) : ((k >> g.n1) >> logB2);
+    };
+    t.goff2.assign(g.ngroups2 + 1, 0);
+    for (int m = 0; m < M; ++m) t.goff2[grp2(omega[m]) + 1]++;
+    for (int q = 0; q < g.ngroups2; ++q) t.goff2[q + 1] += t.goff2[q];
+    std::vector<int32_t> fill(t.goff2.begin(), t.goff2.end() - 1);
+    t.ent2_k.resize(M);
+    t.pos1.resize(M);
+    for (int m = 0; m < M; ++m) {
+      const int q = fill[grp2(omega[m])]++;
+      t.ent2_k[q] = omega[m];
+      t.pos1[q] = inv[m];
+    }
+  } else {
+    t.ent2_k.clear();
+    t.goff2.clear();
+    t.pos1.clear();
+  }
   // twiddles e^{+2 pi i q / N}: lo for q < 2^twS, hi for q * 2^twS, q < N >> twS
   const int nlo = 1 << g.twS, nhi = g.N >> g.twS;
   t.tw64.resize(nlo + nhi);
@@ -79,10 +109,20 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
   }
 }
 
+const Tune& tune() {
+  static const Tune t = [] {
+    Tune v;
+    if (const char* e = std::getenv("FCMP_TILE")) v.tile = std::max(256, std::min(8192, std::atoi(e)));
+    if (const char* e = std::getenv("FCMP_THREADS")) v.threads = std::max(64, std::min(256, std::atoi(e)));
+    return v;
+  }();
+  return t;
+}
+
 static int pick_threads(int tile_n) {
-  int t = tile_n / 4;
+  int t = tile_n / 8;
   if (t < 64) t = 64;
-  if (t > 256) t = 256;
+  if (t > tune().threads) t = tune().threads;
   return t;
 }
 
@@ -102,6 +142,14 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   p.excl = out.excl;
   p.inst_excl = isx;
   p.inst_goff = isg;
+  p.taps_lam = in.taps_lam; p.taps_x = in.taps_x; p.ntaps = in.ntaps;
+  p.inst_taps_lam = in.inst_lam; p.inst_taps_x = in.inst_x;
+  p.resid = 0;
+  p.ent2_k = out.ent2_k; p.goff2 = out.goff2; p.pos1 = out.pos1; p.nent2 = out.nent2;
+  p.yres = out.yres; p.yres_kind = out.yres_kind; p.rout = out.rout; p.r_kind = out.r_kind;
+  p.inst_ent2 = out.inst_ent2; p.inst_goff2 = out.inst_goff2;
+  p.inst_yres = out.inst_yres; p.inst_rout = out.inst_rout;
+  p.excl_mode = 0;
   if (single_ok(vk, g.N)) {
     p.L = g.N; p.logL = g.logN; p.B = 1;
     p.in_mode = in.mode; p.in_kind = in.kind; p.in = in.ptr;
@@ -118,6 +166,10 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
     p.partial = out.partial; p.inst_part = isp;
     p.nthreads = pick_threads(g.N);
     p.role = 0;
+    p.resid = out.resid ? 1 : 0;
+    p.goff2 = nullptr;
+    p.log_out_es = 0;
+    if (out.partial && out.excl) p.excl_mode = 1;
     return launch_xform(vk, fft, p, 1, ninst, st);
   }
   const int N1 = 1 << g.n1, N2 = 1 << g.n2;
@@ -133,7 +185,8 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   a.out_ss = 1; a.out_es = N1; a.inst_out = isn; a.inst_out2 = 0;
   a.inter_tw = fft ? 1 : 0;
   a.scale = 1.0;
-  a.partial = nullptr; a.excl = nullptr;
+  a.partial = nullptr; a.excl = nullptr; a.excl_mode = 0;
+  a.resid = 0;
   a.nthreads = pick_threads(a.L * a.B);
   a.role = 1;
   hipError_t e = launch_xform(vk, fft, a, N1 / g.B1, ninst, st);
@@ -154,6 +207,12 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   b.partial = out.partial; b.inst_part = isp;
   b.nthreads = pick_threads(b.L * b.B);
   b.role = 2;
+  b.resid = out.resid ? 1 : 0;
+  b.log_out_es = fft ? g.n2 : 0;
+  if (out.partial && out.excl) {
+    if (!fft) b.excl_mode = 1;
+    else if ((N2 & 31) == 0 && g.B2 <= 32) b.excl_mode = 2;
+  }
   return launch_xform(vk, fft, b, N2 / g.B2, ninst, st);
 }
 

@@ -23,7 +23,17 @@ struct Geo {
   int B1 = 1, B2 = 1;
   bool grouped = false;
   int ngroups = 1;           // pass-1 workgroups = N1 / B1
+  int ngroups2 = 1;          // pass-2 workgroups = N2 / B2
+  bool same_out = true;      // pass-2 output groups coincide with pass-1 input groups
 };
+
+// Launch-shape knobs (FCMP_TILE: values per workgroup tile in the two-pass
+// transforms; FCMP_THREADS: threads per transform workgroup).
+struct Tune {
+  int tile = 2048;
+  int threads = 256;
+};
+const Tune& tune();
 
 bool single_ok(int vk, int N);
 Geo make_geo(bool fourier, int N);
@@ -31,6 +41,7 @@ int transform_partials(int vk, const Geo& g);   // partials written by a transfo
 
 struct HostTables {
   std::vector<int32_t> ent_k, perm, goff;   // entry order (grouped or Omega order)
+  std::vector<int32_t> ent2_k, goff2, pos1; // rows grouped by pass-2 output workgroup
   std::vector<double2> tw64;                // lo (2^twS) then hi (N >> twS), sign +
   std::vector<float2> tw32;
 };
@@ -38,12 +49,23 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t);
 
 struct TwDev { const void* lo; const void* hi; };
 struct EntDev { const int32_t* ent_k; const int32_t* goff; int M; };
-struct XSrc { int mode; int kind; const void* ptr; };
+struct XSrc {
+  int mode; int kind; const void* ptr;
+  // IN_TAPS
+  const int32_t* taps_lam = nullptr; const void* taps_x = nullptr; int ntaps = 0;
+  int64_t inst_lam = 0, inst_x = 0;
+};
 struct XDst {
   void* out = nullptr; int kind = -1;
   void* out2 = nullptr; int kind2 = -1;
   Sel* partial = nullptr; const uint32_t* excl = nullptr;
   double scale = 1.0;
+  // residual output (see XParams)
+  bool resid = false;
+  const int32_t* ent2_k = nullptr; const int32_t* goff2 = nullptr; const int32_t* pos1 = nullptr;
+  int nent2 = 0;
+  const void* yres = nullptr; int yres_kind = 0; void* rout = nullptr; int r_kind = 0;
+  int64_t inst_ent2 = 0, inst_goff2 = 0, inst_yres = 0, inst_rout = 0;
 };
 
 // One N-point transform (sign +1: U^H, -1: U) of the zero-filled entries or

@@ -20,7 +20,7 @@ inline int vnarrow_kind(int vk) { return vcomplex(vk) ? V_C64 : V_F32; }
 // (bit-reversed placement on input, natural order out); the WHT is the
 // in-place natural-order form.  The identification argmax can be fused into
 // the output loop.
-enum InMode { IN_DENSE = 0, IN_SPARSE = 1, IN_SPARSE_ONES = 2 };
+enum InMode { IN_DENSE = 0, IN_SPARSE = 1, IN_SPARSE_ONES = 2, IN_TAPS = 3 };
 
 struct XParams {
   int L, logL, B;          // transform length and sequences per workgroup
@@ -48,12 +48,23 @@ struct XParams {
   int64_t inst_in, inst_ent, inst_goff, inst_out, inst_out2, inst_part, inst_excl;
   int nthreads;
   int role;                // 0 single workgroup, 1 pass 1, 2 pass 2 (profiler name only)
+  // IN_TAPS: the sparse vector S_Lambda^T x from (lam, x) pairs
+  const int32_t* taps_lam; const void* taps_x; int ntaps;
+  int64_t inst_taps_lam, inst_taps_x;
+  // residual output: r[q] = yres[q] - out(k) for the rows k of Omega this
+  // workgroup produces (entries [goff2[g], goff2[g+1]) of ent2_k; q = pos1[e])
+  int resid;
+  const int32_t* ent2_k; const int32_t* goff2; const int32_t* pos1; int nent2;
+  const void* yres; int yres_kind; void* rout; int r_kind; int log_out_es;
+  int64_t inst_ent2, inst_goff2, inst_yres, inst_rout;
+  // staging of exclusion bits: 0 none, 1 contiguous outputs, 2 strided outputs
+  int excl_mode;
 };
 
 // vk: VKind of the transform arithmetic; fft: Fourier (else Hadamard)
 hipError_t launch_xform(int vk, bool fft, const XParams& p, int groups, int ninst,
                         hipStream_t st);
-size_t xform_lds_bytes(int vk, bool fft, int L, int B, int N, int twS);
+size_t xform_lds_bytes(int vk, bool fft, const XParams& p);
 
 // ------------------------------------------------------------------ residual
 // r[e] = y[e] - sum_tau U(k_e, lam_tau) x_tau for the current support, in FP64,
@@ -113,8 +124,13 @@ struct LParams {
   uint32_t* excl;
   Status* status;
   int64_t inst_part, inst_c, inst_h0, inst_W, inst_z, inst_x, inst_lam, inst_excl;
+  // scratch for the split update (nullable: then one workgroup per instance)
+  void* wbuf; int64_t inst_wbuf;          // w = W g, K values
+  void* vpart; int64_t inst_vpart;        // 16 partial rows of w^H W, K values each
+  int64_t vpart_stride;
 };
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st);
+int ls_split_groups(int t);   // workgroups per instance used at iteration t
 
 // ------------------------------------------------------------------ utilities
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

@@ -108,9 +108,8 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
     const Wd wi = w[i];
 #pragma unroll
     for (int q = 0; q < L_KPT; ++q) {
-      if (q >= nq) break;
       const int k = tid + q * L_THREADS;
-      if (k <= i) {
+      if (q < nq && k <= i) {
         if constexpr (FOURIER) { const double2 t = cmulc(wi, Wi[k]); acc[q].x += t.x; acc[q].y += t.y; }
         else acc[q] += wi * Wi[k];
       }
@@ -163,7 +162,218 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same update split over G workgroups per instance for long supports:
+//   ls_a: identification, Gram column, w = W g (rows cyclic over G*4 waves)
+//   ls_b: d, and partial sums of w^H W over the rows i = gid (mod G)
+//   ls_c: v = -(sum over the G partials, in order)/d, new row of W, z and x
+// Every reduction has a fixed order, so results depend on t only.
+template <bool FOURIER>
+__global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
+  using Wd = typename std::conditional<FOURIER, double2, double>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ Sel red[16];
+  const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
+  Status* st = p.status + inst;
+  if (st->done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = p.t - 1;
+  Wd* g = (Wd*)smem_raw;
+  const Sel* part = p.partial + (int64_t)inst * p.inst_part;
+  double bk = -1.0;
+  int64_t bi = -1;
+  for (int e = tid; e < p.npart; e += L_THREADS) {
+    const Sel s = part[e];
+    if (s.idx >= 0 && sel_better(s.key, s.idx, bk, bi)) { bk = s.key; bi = s.idx; }
+  }
+  const Sel best = block_sel_reduce(bk, bi, red);
+  if (best.idx < 0 || !(best.key > 0.0)) {
+    if (gid == 0 && tid == 0) st->done = 1;
+    return;
+  }
+  const uint32_t j = (uint32_t)best.idx;
+  if (gid == 0 && tid == 0) {
+    st->cur_j = (int32_t)j;
+    st->last_key = best.key;
+  }
+  const uint32_t mask = (uint32_t)p.N - 1u;
+  const int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
+  const Wd* c64 = (const Wd*)p.c64 + (int64_t)inst * p.inst_c;
+  const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
+  Wd* wout = (Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
+  for (int i = tid; i < n; i += L_THREADS) g[i] = c64[perm_index(FOURIER, (uint32_t)lam[i], j, mask)];
+  __syncthreads();
+  for (int i = gid * (L_THREADS / 64) + wave; i < n; i += G * (L_THREADS / 64)) {
+    const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
+    Wd s = vzero(Wd());
+    for (int k = lane; k <= i; k += 64) {
+      if constexpr (FOURIER) { const double2 t = cmul(Wi[k], g[k]); s.x += t.x; s.y += t.y; }
+      else s += Wi[k] * g[k];
+    }
+    if constexpr (FOURIER) { s.x = wave_sum(s.x); s.y = wave_sum(s.y); }
+    else s = wave_sum(s);
+    if (lane == 0) wout[i] = s;
+  }
+}
+
+template <bool FOURIER>
+__device__ __forceinline__ bool ls_d(const LParams& p, int inst, int n, double* dred,
+                                     double& invd, double& wzr, double& wzi) {
+  using Wd = typename std::conditional<FOURIER, double2, double>::type;
+  const Wd* w = (const Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
+  const Wd* z = (const Wd*)p.z + (int64_t)inst * p.inst_z;
+  double nw = 0.0;
+  wzr = 0.0;
+  wzi = 0.0;
+  for (int i = threadIdx.x; i < n; i += L_THREADS) {
+    const Wd wi = w[i];
+    nw += vmag2(wi);
+    if constexpr (FOURIER) { const double2 t = cmulc(wi, z[i]); wzr += t.x; wzi += t.y; }
+    else wzr += wi * z[i];
+  }
+  nw = block_sum(nw, dred);
+  wzr = block_sum(wzr, dred);
+  if (FOURIER) wzi = block_sum(wzi, dred);
+  const Wd* c64 = (const Wd*)p.c64 + (int64_t)inst * p.inst_c;
+  double gamma;
+  if constexpr (FOURIER) gamma = c64[0].x; else gamma = c64[0];
+  const double d2 = gamma - nw;
+  if (!(d2 > 1e-13 * gamma)) return false;
+  invd = 1.0 / sqrt(d2);
+  return true;
+}
+
+template <bool FOURIER>
+__global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
+  using Wd = typename std::conditional<FOURIER, double2, double>::type;
+  __shared__ double dred[16];
+  const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
+  Status* st = p.status + inst;
+  if (st->done) return;
+  const int tid = threadIdx.x;
+  const int n = p.t - 1;
+  double invd, wzr, wzi;
+  if (!ls_d<FOURIER>(p, inst, n, dred, invd, wzr, wzi)) {
+    if (gid == 0 && tid == 0) { st->numeric = 1; st->done = 1; }
+    return;
+  }
+  const Wd* w = (const Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
+  const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
+  Wd acc[L_KPT];
+#pragma unroll
+  for (int q = 0; q < L_KPT; ++q) acc[q] = vzero(Wd());
+  const int nq = (n + L_THREADS - 1) / L_THREADS;
+  for (int i = gid; i < n; i += G) {
+    const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
+    const Wd wi = w[i];
+#pragma unroll
+    for (int q = 0; q < L_KPT; ++q) {
+      const int k = tid + q * L_THREADS;
+      if (q < nq && k <= i) {
+        if constexpr (FOURIER) { const double2 t = cmulc(wi, Wi[k]); acc[q].x += t.x; acc[q].y += t.y; }
+        else acc[q] += wi * Wi[k];
+      }
+    }
+  }
+  Wd* vp = (Wd*)p.vpart + (int64_t)inst * p.inst_vpart + (int64_t)gid * p.vpart_stride;
+#pragma unroll
+  for (int q = 0; q < L_KPT; ++q) {
+    const int k = tid + q * L_THREADS;
+    if (q < nq && k < n) vp[k] = acc[q];
+  }
+}
+
+template <bool FOURIER>
+__global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int G) {
+  using Wd = typename std::conditional<FOURIER, double2, double>::type;
+  __shared__ double dred[16];
+  const int inst = blockIdx.y, cb = blockIdx.x;
+  Status* st = p.status + inst;
+  if (st->done) return;
+  const int tid = threadIdx.x;
+  const int n = p.t - 1;
+  double invd, wzr, wzi;
+  if (!ls_d<FOURIER>(p, inst, n, dred, invd, wzr, wzi)) return;   // ls_b flagged it
+  const uint32_t j = (uint32_t)st->cur_j;
+  Wd b = ((const Wd*)p.h0 + (int64_t)inst * p.inst_h0)[j];
+  Wd zt;
+  if constexpr (FOURIER) zt = make_double2((b.x - wzr) * invd, (b.y - wzi) * invd);
+  else zt = (b - wzr) * invd;
+  Wd* W = (Wd*)p.W + (int64_t)inst * p.inst_W;
+  Wd* Wn = W + (int64_t)n * (n + 1) / 2;
+  Wd* x = (Wd*)p.x + (int64_t)inst * p.inst_x;
+  const Wd* vp = (const Wd*)p.vpart + (int64_t)inst * p.inst_vpart;
+  const int k = cb * L_THREADS + tid;
+  if (k < n) {
+    Wd s = vzero(Wd());
+    for (int q = 0; q < G; ++q) {
+      const Wd a = vp[(int64_t)q * p.vpart_stride + k];
+      if constexpr (FOURIER) { s.x += a.x; s.y += a.y; } else s += a;
+    }
+    Wd v;
+    if constexpr (FOURIER) {
+      v = make_double2(-s.x * invd, -s.y * invd);
+      const double2 t = cmulc(v, zt);
+      x[k].x += t.x;
+      x[k].y += t.y;
+    } else {
+      v = -s * invd;
+      x[k] += v * zt;
+    }
+    Wn[k] = v;
+  }
+  if (cb == 0 && tid == 0) {
+    if constexpr (FOURIER) {
+      Wn[n] = make_double2(invd, 0.0);
+      x[n] = make_double2(zt.x * invd, zt.y * invd);
+    } else {
+      Wn[n] = invd;
+      x[n] = zt * invd;
+    }
+    Wd* z = (Wd*)p.z + (int64_t)inst * p.inst_z;
+    z[n] = zt;
+    int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
+    lam[n] = (int32_t)j;
+    uint32_t* ex = p.excl + (int64_t)inst * p.inst_excl;
+    ex[j >> 5] |= 1u << (j & 31);
+    st->znorm2 += vmag2(zt);
+    st->iterations = p.t;
+  }
+}
+
+int ls_split_groups(int t) {
+  const int n = t - 1;
+  if (n < 64) return 1;
+  int G = n / 48;
+  if (G < 2) G = 2;
+  if (G > 16) G = 16;
+  return G;
+}
+
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st) {
+  const int G = ls_split_groups(p.t);
+  if (G > 1 && p.wbuf && p.vpart) {
+    const int n = p.t - 1;
+    const size_t wb = p.fourier ? 16 : 8;
+    const size_t lds_a = (size_t)n * wb + 16;
+    const int cblocks = (n + L_THREADS - 1) / L_THREADS;
+    if (p.fourier) {
+      if (lds_a > 65536)
+        hipFuncSetAttribute((const void*)ls_a_kernel<true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_a);
+      hipLaunchKernelGGL(ls_a_kernel<true>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
+      hipLaunchKernelGGL(ls_b_kernel<true>, dim3(G, ninst), dim3(L_THREADS), 0, st, p);
+      hipLaunchKernelGGL(ls_c_kernel<true>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
+    } else {
+      if (lds_a > 65536)
+        hipFuncSetAttribute((const void*)ls_a_kernel<false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_a);
+      hipLaunchKernelGGL(ls_a_kernel<false>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
+      hipLaunchKernelGGL(ls_b_kernel<false>, dim3(G, ninst), dim3(L_THREADS), 0, st, p);
+      hipLaunchKernelGGL(ls_c_kernel<false>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
+    }
+    return hipGetLastError();
+  }
   const int n = p.t - 1 > 0 ? p.t - 1 : 1;
   const size_t wb = p.fourier ? 16 : 8;
   const size_t lds = 2 * n * wb + (size_t)n * 4 + 16;

@@ -3,6 +3,7 @@
 #include "plan.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 namespace fcmp {
@@ -43,6 +44,8 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
   P.sK = pad64(K);
   P.sW = pad64(K * (K + 1) / 2);
   P.sG = pad64(P.g.ngroups + 1);
+  P.sG2 = pad64(P.g.ngroups2 + 1);
+  if (const char* e = std::getenv("FCMP_RESID_RATIO")) P.resid_ratio = std::atof(e);
   P.npart = std::max(std::max(transform_partials(P.wk, P.g), transform_partials(P.pk, P.g)),
                      fastcorr_groups((int)N));
   P.sP = pad64(P.npart);
@@ -62,6 +65,15 @@ void plan_layout(fcmp_plan& P, char* base) {
   P.ent_k = cv.take<int32_t>(n * P.sM);
   P.perm = cv.take<int32_t>(n * P.sM);
   P.goff = cv.take<int32_t>(n * P.sG);
+  if (!P.g.same_out) {
+    P.ent2_k = cv.take<int32_t>(n * P.sM);
+    P.goff2 = cv.take<int32_t>(n * P.sG2);
+    P.pos1 = cv.take<int32_t>(n * P.sM);
+  } else {
+    P.ent2_k = P.ent_k;
+    P.goff2 = P.g.grouped ? P.goff : nullptr;
+    P.pos1 = nullptr;
+  }
   P.c64 = cv.take_bytes(n * P.sN * wb);
   P.cp = P.pk == P.wk ? P.c64 : cv.take_bytes(n * P.sN * pb);
   P.y_ent = cv.take_bytes(n * P.sM * wb);
@@ -74,6 +86,8 @@ void plan_layout(fcmp_plan& P, char* base) {
   P.x = cv.take_bytes(n * P.sK * wb);
   P.z = cv.take_bytes(n * P.sK * wb);
   P.W = cv.take_bytes(n * P.sW * wb);
+  P.wbuf = cv.take_bytes(n * P.sK * wb);
+  P.vpart = cv.take_bytes(n * 16 * P.sK * wb);
   P.status = cv.take<Status>(n);
   P.dptrs = cv.take<void*>(3 * n);
   P.total = cv.total();
@@ -101,12 +115,28 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
   const int64_t n = P.n, M = P.shape.M;
   std::vector<int32_t> ent((size_t)(n * P.sM), 0), perm((size_t)(n * P.sM), 0),
       goff((size_t)(n * P.sG), 0);
+  std::vector<int32_t> ent2, goff2, pos1;
+  if (!P.g.same_out) {
+    ent2.assign((size_t)(n * P.sM), 0);
+    goff2.assign((size_t)(n * P.sG2), 0);
+    pos1.assign((size_t)(n * P.sM), 0);
+  }
   HostTables t;
   for (int64_t b = 0; b < n; ++b) {
     build_tables(P.g, probs[b].omega, (int)M, t);
     std::memcpy(&ent[b * P.sM], t.ent_k.data(), M * 4);
     std::memcpy(&perm[b * P.sM], t.perm.data(), M * 4);
     std::memcpy(&goff[b * P.sG], t.goff.data(), t.goff.size() * 4);
+    if (!P.g.same_out) {
+      std::memcpy(&ent2[b * P.sM], t.ent2_k.data(), M * 4);
+      std::memcpy(&goff2[b * P.sG2], t.goff2.data(), t.goff2.size() * 4);
+      std::memcpy(&pos1[b * P.sM], t.pos1.data(), M * 4);
+    }
+  }
+  if (!P.g.same_out) {
+    HIP_TRY(hipMemcpyAsync(P.ent2_k, ent2.data(), ent2.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(P.goff2, goff2.data(), goff2.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(P.pos1, pos1.data(), pos1.size() * 4, hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipMemcpyAsync(P.tw64, t.tw64.data(), t.tw64.size() * sizeof(double2),
                          hipMemcpyHostToDevice, st));
@@ -191,6 +221,8 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
   lp.lam = P.lam; lp.excl = P.excl; lp.status = P.status;
   lp.inst_part = P.sP; lp.inst_c = P.sN; lp.inst_h0 = P.sN; lp.inst_W = P.sW;
   lp.inst_z = P.sK; lp.inst_x = P.sK; lp.inst_lam = P.sK; lp.inst_excl = P.sE;
+  lp.wbuf = P.wbuf; lp.inst_wbuf = P.sK;
+  lp.vpart = P.vpart; lp.inst_vpart = 16 * P.sK; lp.vpart_stride = P.sK;
   lp.t = 1;
   {
     ProfScope ps(FCMP_PHASE_LS, st);
@@ -212,7 +244,24 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
       fp.inst_h = 0; fp.inst_part = P.sP; fp.inst_excl = P.sE;
       HIP_TRY(launch_fastcorr(fp, n, &npart, st));
     } else {
-      {
+      const bool tresid =
+          (double)M * (double)(t - 1) > P.resid_ratio * (double)N * (double)g.logN;
+      if (tresid) {
+        // residual through one FP64 forward transform of S_Lambda^T x
+        ProfScope ps(FCMP_PHASE_RESID, st);
+        XSrc src{IN_TAPS, P.wk, nullptr};
+        src.taps_lam = P.lam; src.taps_x = P.x; src.ntaps = t - 1;
+        src.inst_lam = P.sK; src.inst_x = P.sK;
+        XDst d;
+        d.scale = inv_sqrt_n;
+        d.resid = true;
+        d.ent2_k = P.ent2_k; d.goff2 = P.goff2; d.pos1 = P.pos1; d.nent2 = M;
+        d.yres = P.y_ent; d.yres_kind = P.wk; d.rout = P.r; d.r_kind = P.pk;
+        d.inst_ent2 = P.sM; d.inst_goff2 = P.g.same_out ? P.sG : P.sG2;
+        d.inst_yres = P.sM; d.inst_rout = P.sM;
+        HIP_TRY(run_transform(P.wk, -1, g, tw_for(P, P.wk), en, src, d, P.tmp, P.status, st, n,
+                              P.sN, P.sM, 0, 0, P.sG));
+      } else {
         ProfScope ps(FCMP_PHASE_RESID, st);
         RParams rp{};
         rp.N = N; rp.logN = g.logN; rp.twS = g.twS; rp.fourier = F; rp.M = M;

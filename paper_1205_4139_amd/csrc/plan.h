@@ -12,7 +12,8 @@ struct fcmp_plan {
   fcmp::Geo g;
   int wk = 0, pk = 0;          // wide and correlation-precision value kinds
   // per-instance strides in elements
-  int64_t sM = 0, sN = 0, sK = 0, sW = 0, sG = 0, sP = 0, sE = 0;
+  int64_t sM = 0, sN = 0, sK = 0, sW = 0, sG = 0, sG2 = 0, sP = 0, sE = 0;
+  double resid_ratio = 1.0;    // transform residual when M (t-1) > ratio * N log2 N
   int npart = 1;
   // shared
   double2* tw64 = nullptr;
@@ -21,6 +22,9 @@ struct fcmp_plan {
   int32_t* ent_k = nullptr;
   int32_t* perm = nullptr;
   int32_t* goff = nullptr;
+  int32_t* ent2_k = nullptr;   // rows grouped by pass-2 output (absent when identical)
+  int32_t* goff2 = nullptr;
+  int32_t* pos1 = nullptr;
   void* c64 = nullptr;
   void* cp = nullptr;
   void* y_ent = nullptr;
@@ -33,6 +37,8 @@ struct fcmp_plan {
   void* x = nullptr;
   void* z = nullptr;
   void* W = nullptr;
+  void* wbuf = nullptr;        // split least squares: w and the partial rows
+  void* vpart = nullptr;
   fcmp::Status* status = nullptr;
   void** dptrs = nullptr;      // 3n device pointers: y, support, x
   std::vector<const void*> last_ptrs;

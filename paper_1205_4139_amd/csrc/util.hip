@@ -97,7 +97,7 @@ __global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, i
   s = block_sum(s, dred);
   if (threadIdx.x == 0) {
     Status z;
-    z.done = 0; z.numeric = 0; z.iterations = 0; z.pad = 0;
+    z.done = 0; z.numeric = 0; z.iterations = 0; z.cur_j = -1;
     z.znorm2 = 0.0; z.ynorm2 = s; z.last_key = 0.0; z.pad2 = 0.0;
     st[inst] = z;
   }

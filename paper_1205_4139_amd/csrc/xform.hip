@@ -74,107 +74,144 @@ template <class V> __device__ __forceinline__ V mul_i(V a, int sign) {
   return r;
 }
 
-// In-place natural-order WHT of B interleaved sequences of length L
-// (element (i, c) at lds_addr(i*B + c)): radix-4 stages, one radix-2 stage
-// when log2 L is odd.
-template <class V>
-__device__ void lds_wht(V* t, int L, int logL, int B, int logB) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  int logh = 0;
-  for (; logh + 2 <= logL; logh += 2) {
-    const int h = 1 << logh;
-    const int ngrp = (B * L) >> 2;
-    for (int grp = tid; grp < ngrp; grp += nt) {
-      const int c = grp & (B - 1);
-      const int q = grp >> logB;
-      const int k = q & (h - 1);
-      const int base = ((q >> logh) << (logh + 2)) + k;
-      const int a0 = lds_addr(base * B + c), a1 = lds_addr((base + h) * B + c);
-      const int a2 = lds_addr((base + 2 * h) * B + c), a3 = lds_addr((base + 3 * h) * B + c);
-      const V e0 = t[a0], e1 = t[a1], e2 = t[a2], e3 = t[a3];
-      const V s01 = vadd(e0, e1), d01 = vsub(e0, e1), s23 = vadd(e2, e3), d23 = vsub(e2, e3);
-      t[a0] = vadd(s01, s23);
-      t[a1] = vadd(d01, d23);
-      t[a2] = vsub(s01, s23);
-      t[a3] = vsub(d01, d23);
-    }
-    __syncthreads();
-  }
-  if (logh < logL) {
-    const int h = 1 << logh;
-    const int ngrp = (B * L) >> 1;
-    for (int grp = tid; grp < ngrp; grp += nt) {
-      const int c = grp & (B - 1);
-      const int q = grp >> logB;
-      const int k = q & (h - 1);
-      const int base = ((q >> logh) << (logh + 1)) + k;
-      const int a0 = lds_addr(base * B + c), a1 = lds_addr((base + h) * B + c);
-      const V e0 = t[a0], e1 = t[a1];
-      t[a0] = vadd(e0, e1);
-      t[a1] = vsub(e0, e1);
-    }
-    __syncthreads();
+// e^{sign 2 pi i j / 2^(s+1)} for s < 4, j < 2^s: the constant twiddles inside
+// a radix-16 block (cos and sin of multiples of pi/8).
+template <int S, int J> struct CTw;
+#define FCMP_CTW(S_, J_, C_, SN_) \
+  template <> struct CTw<S_, J_> { static constexpr double c = C_; static constexpr double s = SN_; };
+FCMP_CTW(0, 0, 1.0, 0.0)
+FCMP_CTW(1, 0, 1.0, 0.0)
+FCMP_CTW(1, 1, 0.0, 1.0)
+FCMP_CTW(2, 0, 1.0, 0.0)
+FCMP_CTW(2, 1, 0.70710678118654752440, 0.70710678118654752440)
+FCMP_CTW(2, 2, 0.0, 1.0)
+FCMP_CTW(2, 3, -0.70710678118654752440, 0.70710678118654752440)
+FCMP_CTW(3, 0, 1.0, 0.0)
+FCMP_CTW(3, 1, 0.92387953251128675613, 0.38268343236508977173)
+FCMP_CTW(3, 2, 0.70710678118654752440, 0.70710678118654752440)
+FCMP_CTW(3, 3, 0.38268343236508977173, 0.92387953251128675613)
+FCMP_CTW(3, 4, 0.0, 1.0)
+FCMP_CTW(3, 5, -0.38268343236508977173, 0.92387953251128675613)
+FCMP_CTW(3, 6, -0.70710678118654752440, 0.70710678118654752440)
+FCMP_CTW(3, 7, -0.92387953251128675613, 0.38268343236508977173)
+#undef FCMP_CTW
+
+// b * e^{sign 2 pi i J / 2^(S+1)}
+template <int S, int J, class V>
+__device__ __forceinline__ V twc(V b, int sign) {
+  using T = decltype(b.x);
+  if constexpr (J == 0) {
+    return b;
+  } else if constexpr (CTw<S, J>::c == 0.0) {   // +-i
+    return mul_i(b, sign);
+  } else {
+    V w;
+    w.x = (T)CTw<S, J>::c;
+    w.y = sign > 0 ? (T)CTw<S, J>::s : -(T)CTw<S, J>::s;
+    return cmul(b, w);
   }
 }
 
-// In-place decimation-in-time DFT with kernel e^{sign 2 pi i j k / L} of B
-// interleaved sequences whose elements were placed in bit-reversed order;
-// the result is in natural order.  Stage twiddles w_{m}^k = W_N^{k N/m}.
-template <class V>
-__device__ void lds_fft(V* t, int L, int logL, int B, int logB, const V* lo, const V* hi,
-                        int twS, int logN, int sign) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  int logh = 0;
-  for (; logh + 2 <= logL; logh += 2) {
-    const int h = 1 << logh;
-    const int sh = logN - logh - 2;
-    const int ngrp = (B * L) >> 2;
-    for (int grp = tid; grp < ngrp; grp += nt) {
-      const int c = grp & (B - 1);
-      const int q = grp >> logB;
-      const int k = q & (h - 1);
-      const int base = ((q >> logh) << (logh + 2)) + k;
-      const int a0 = lds_addr(base * B + c), a1 = lds_addr((base + h) * B + c);
-      const int a2 = lds_addr((base + 2 * h) * B + c), a3 = lds_addr((base + 3 * h) * B + c);
-      const V e0 = t[a0], e1 = t[a1], e2 = t[a2], e3 = t[a3];
-      const uint32_t pk = (uint32_t)k << sh;
-      const V w2 = tw_lookup(lo, hi, pk, twS, sign);        // w_{4h}^k
-      const V w1 = tw_lookup(lo, hi, pk << 1, twS, sign);   // w_{2h}^k
-      const V w3 = mul_i(w2, sign);                         // w_{4h}^{k+h}
-      const V t1 = cmul(w1, e1), t3 = cmul(w1, e3);
-      const V e0p = vadd(e0, t1), e1p = vsub(e0, t1), e2p = vadd(e2, t3), e3p = vsub(e2, t3);
-      const V u2 = cmul(w2, e2p), u3 = cmul(w3, e3p);
-      t[a0] = vadd(e0p, u2);
-      t[a2] = vsub(e0p, u2);
-      t[a1] = vadd(e1p, u3);
-      t[a3] = vsub(e1p, u3);
+// Radix-2 DIT sub-stage s over the R = 2^S registers of one block: pairs
+// (m, m + 2^s) with twiddle b[s] * w_{2^(s+1)}^(m mod 2^s).
+template <int S, int s, int M, class V>
+__device__ __forceinline__ void dit_pairs(V* x, const V* b, int sign) {
+  if constexpr (M < (1 << S)) {
+    constexpr int half = 1 << s;
+    if constexpr ((M & half) == 0) {
+      const V w = twc<s, (M & (half - 1))>(b[s], sign);
+      const V t = cmul(w, x[M + half]);
+      x[M + half] = vsub(x[M], t);
+      x[M] = vadd(x[M], t);
     }
-    __syncthreads();
+    dit_pairs<S, s, M + 1>(x, b, sign);
   }
-  if (logh < logL) {
-    const int h = 1 << logh;
-    const int sh = logN - logh - 1;
-    const int ngrp = (B * L) >> 1;
-    for (int grp = tid; grp < ngrp; grp += nt) {
-      const int c = grp & (B - 1);
-      const int q = grp >> logB;
-      const int k = q & (h - 1);
-      const int base = ((q >> logh) << (logh + 1)) + k;
-      const int a0 = lds_addr(base * B + c), a1 = lds_addr((base + h) * B + c);
-      const V e0 = t[a0], e1 = t[a1];
-      const V w = tw_lookup(lo, hi, (uint32_t)k << sh, twS, sign);
-      const V t1 = cmul(w, e1);
-      t[a0] = vadd(e0, t1);
-      t[a1] = vsub(e0, t1);
+}
+
+template <int S, int s, class V>
+__device__ __forceinline__ void dit_block(V* x, const V* b, int sign) {
+  if constexpr (s < S) {
+    dit_pairs<S, s, 0>(x, b, sign);
+    dit_block<S, s + 1>(x, b, sign);
+  }
+}
+
+template <int S, int s, int M, class V>
+__device__ __forceinline__ void wht_pairs(V* x) {
+  if constexpr (M < (1 << S)) {
+    constexpr int half = 1 << s;
+    if constexpr ((M & half) == 0) {
+      const V a = x[M], c = x[M + half];
+      x[M] = vadd(a, c);
+      x[M + half] = vsub(a, c);
     }
-    __syncthreads();
+    wht_pairs<S, s, M + 1>(x);
+  }
+}
+
+template <int S, int s, class V>
+__device__ __forceinline__ void wht_block(V* x) {
+  if constexpr (s < S) {
+    wht_pairs<S, s, 0>(x);
+    wht_block<S, s + 1>(x);
+  }
+}
+
+// One radix-2^S stage over the LDS tile: each group holds the 2^S elements
+// base + k + m h (m < 2^S) of one sequence in registers and applies S
+// consecutive radix-2 levels (spans h .. 2^(S-1) h) to them.  The Fourier
+// form is the in-place decimation-in-time DFT on bit-reversed input, the
+// Hadamard form the in-place natural-order WHT.  Element (i, c) of the tile
+// lives at lds_addr(i*B + c).
+template <int S, bool FFT, class V>
+__device__ __forceinline__ void lds_stage(V* t, int L, int B, int logB, int logh, const V* lo,
+                                          const V* hi, int twS, int logN, int sign) {
+  constexpr int R = 1 << S;
+  const int h = 1 << logh;
+  const int ngrp = (B * L) >> S;
+  for (int grp = threadIdx.x; grp < ngrp; grp += blockDim.x) {
+    const int c = grp & (B - 1);
+    const int q = grp >> logB;
+    const int k = q & (h - 1);
+    const int base = ((q >> logh) << (logh + S)) + k;
+    V x[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) x[m] = t[lds_addr((base + m * h) * B + c)];
+    if constexpr (FFT) {
+      V b[S];
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+        b[s] = tw_lookup(lo, hi, (uint32_t)k << (logN - logh - s - 1), twS, sign);  // w_{2^(s+1) h}^k
+      dit_block<S, 0>(x, b, sign);
+    } else {
+      wht_block<S, 0>(x);
+    }
+#pragma unroll
+    for (int m = 0; m < R; ++m) t[lds_addr((base + m * h) * B + c)] = x[m];
+  }
+  __syncthreads();
+}
+
+// B interleaved length-L transforms in LDS: radix-8 stages from the
+// smallest span up, then one radix-2/4 stage for the remaining levels (radix
+// 8 keeps the block in about 60 VGPRs, so four waves per SIMD stay resident).
+template <bool FFT, class V>
+__device__ void lds_transform(V* t, int L, int logL, int B, int logB, const V* lo, const V* hi,
+                              int twS, int logN, int sign) {
+  int logh = 0;
+  for (; logh + 3 <= logL; logh += 3)
+    lds_stage<3, FFT>(t, L, B, logB, logh, lo, hi, twS, logN, sign);
+  switch (logL - logh) {
+    case 2: lds_stage<2, FFT>(t, L, B, logB, logh, lo, hi, twS, logN, sign); break;
+    case 1: lds_stage<1, FFT>(t, L, B, logB, logh, lo, hi, twS, logN, sign); break;
+    default: break;
   }
 }
 
 // ROLE only names the launch for profilers: 0 one workgroup per transform,
 // 1 first pass (columns), 2 second pass (rows).
 template <class V, bool FFT, int ROLE>
-__global__ void __launch_bounds__(1024) xform_kernel(XParams p) {
+__global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int inst = blockIdx.y;
   if (p.status && p.status[inst].done) return;
@@ -211,6 +248,24 @@ __global__ void __launch_bounds__(1024) xform_kernel(XParams p) {
       const int pos = FFT ? bitrev(i, logL) : i;
       tile[lds_addr(pos * B + c)] = v;
     }
+  } else if (p.in_mode == IN_TAPS) {
+    // zero-filled sparse vector S_Lambda^T x: this workgroup keeps the taps
+    // whose column falls in its sequences
+    const V z = vzero(V());
+    for (int e = tid; e < tile_alloc; e += nt) tile[e] = z;
+    __syncthreads();
+    const int32_t* tl = p.taps_lam + (int64_t)inst * p.inst_taps_lam;
+    const int mask1 = (1 << p.logN1) - 1;
+    for (int e = tid; e < p.ntaps; e += nt) {
+      const int k = tl[e];
+      const int i = k >> p.logN1;
+      const int c = (k & mask1) - s0;
+      if (c >= 0 && c < B) {
+        const V v = load_as<V>(p.taps_x, (int64_t)inst * p.inst_taps_x + e, p.in_kind);
+        const int pos = FFT ? bitrev(i, logL) : i;
+        tile[lds_addr(pos * B + c)] = v;
+      }
+    }
   } else {
     const V z = vzero(V());
     for (int e = tid; e < tile_alloc; e += nt) tile[e] = z;
@@ -236,13 +291,52 @@ __global__ void __launch_bounds__(1024) xform_kernel(XParams p) {
   __syncthreads();
 
   // ---- transform
-  if constexpr (FFT) lds_fft<V>(tile, L, logL, B, logB, twlo, twhi, p.twS, p.logN, p.sign);
-  else lds_wht<V>(tile, L, logL, B, logB);
+  lds_transform<FFT>(tile, L, logL, B, logB, twlo, twhi, p.twS, p.logN, p.sign);
+
+  // ---- residual output: r = y - (S_Omega U s) at the rows of Phi this
+  // workgroup produced (forward transform of the support, Algorithm 1.1 step 7)
+  if (p.resid) {
+    int lo = 0, hi = p.nent2;
+    if (p.goff2) {
+      const int32_t* go = p.goff2 + (int64_t)inst * p.inst_goff2;
+      lo = go[g];
+      hi = go[g + 1];
+    }
+    const int32_t* ek = p.ent2_k + (int64_t)inst * p.inst_ent2;
+    const int32_t* pos1 = p.pos1 ? p.pos1 + (int64_t)inst * p.inst_ent2 : nullptr;
+    const int esmask = (1 << p.log_out_es) - 1;
+    for (int e = lo + tid; e < hi; e += nt) {
+      const int k = ek[e];
+      int c, j;
+      if (p.out_es == 1) { j = k & (L - 1); c = (k >> logL) - s0; }
+      else { c = (k & esmask) - s0; j = k >> p.log_out_es; }
+      const V v = vscale(tile[lds_addr(j * B + c)], p.scale);
+      const int64_t q = pos1 ? (int64_t)pos1[e] : (int64_t)e;
+      const V yv = load_as<V>(p.yres, (int64_t)inst * p.inst_yres + q, p.yres_kind);
+      store_as(p.rout, (int64_t)inst * p.inst_rout + q, p.r_kind, vsub(yv, v));
+    }
+    return;
+  }
 
   // ---- store / identify
   double bkey = -1.0;
   int64_t bidx = -1;
   const uint32_t* excl = p.excl ? p.excl + (int64_t)inst * p.inst_excl : nullptr;
+  // stage the exclusion bits this workgroup needs
+  uint32_t* xw = (uint32_t*)(red + 16);
+  int64_t xbase = 0;
+  if (p.partial && excl && p.excl_mode) {
+    if (p.excl_mode == 1) {
+      const int64_t o0 = (int64_t)s0 * p.out_ss;
+      xbase = o0 >> 5;
+      const int nw = (int)(((o0 + tile_n - 1) >> 5) - xbase + 1);
+      for (int e = tid; e < nw; e += nt) xw[e] = excl[xbase + e];
+    } else {
+      const int64_t wstride = p.out_es >> 5;
+      for (int e = tid; e < L; e += nt) xw[e] = excl[(s0 >> 5) + e * wstride];
+    }
+    __syncthreads();
+  }
   for (int e = tid; e < tile_n; e += nt) {
     int c, j;
     if (p.out_es == 1) { c = e >> logL; j = e & (L - 1); }
@@ -259,7 +353,13 @@ __global__ void __launch_bounds__(1024) xform_kernel(XParams p) {
     if (p.out_kind >= 0) store_as(p.out, (int64_t)inst * p.inst_out + o, p.out_kind, v);
     if (p.out2_kind >= 0) store_as(p.out2, (int64_t)inst * p.inst_out2 + o, p.out2_kind, v);
     if (p.partial) {
-      if (!excl || !bit_is_set(excl, o)) {
+      bool ex = false;
+      if (excl) {
+        if (p.excl_mode == 1) ex = (xw[(o >> 5) - xbase] >> (o & 31)) & 1u;
+        else if (p.excl_mode == 2) ex = (xw[j] >> ((s0 + c) & 31)) & 1u;
+        else ex = bit_is_set(excl, o);
+      }
+      if (!ex) {
         const double kk = vmag2(v);
         if (sel_better(kk, o, bkey, bidx)) { bkey = kk; bidx = o; }
       }
@@ -271,14 +371,16 @@ __global__ void __launch_bounds__(1024) xform_kernel(XParams p) {
   }
 }
 
-size_t xform_lds_bytes(int vk, bool fft, int L, int B, int N, int twS) {
+size_t xform_lds_bytes(int vk, bool fft, const XParams& p) {
   const size_t vb = vbytes(vk);
-  const size_t tile_n = (size_t)B * L;
+  const size_t tile_n = (size_t)p.B * p.L;
   const size_t tile_alloc = tile_n + (tile_n >> 5) + 1;
-  const size_t ntw = fft ? ((size_t)1 << twS) + ((size_t)N >> twS) : 0;
+  const size_t ntw = fft ? ((size_t)1 << p.twS) + ((size_t)p.N >> p.twS) : 0;
   size_t bytes = (tile_alloc + ntw) * vb;
   bytes = (bytes + 15) & ~(size_t)15;
   bytes += 16 * sizeof(Sel);
+  if (p.excl_mode == 1) bytes += (tile_n / 32 + 2) * 4;
+  else if (p.excl_mode == 2) bytes += (size_t)p.L * 4;
   return bytes;
 }
 
@@ -303,7 +405,7 @@ static hipError_t launch_t(const XParams& p, int groups, int ninst, size_t lds, 
 
 hipError_t launch_xform(int vk, bool fft, const XParams& p, int groups, int ninst,
                         hipStream_t st) {
-  const size_t lds = xform_lds_bytes(vk, fft, p.L, p.B, p.N, p.twS);
+  const size_t lds = xform_lds_bytes(vk, fft, p);
   if (fft) {
     if (vk == V_C64) return launch_t<float2, true>(p, groups, ninst, lds, st);
     if (vk == V_C128) return launch_t<double2, true>(p, groups, ninst, lds, st);

@@ -1,0 +1,102 @@
+"""C-ABI checks that need no GPU: every declared symbol is exported, and
+host-side validation rejects bad problems before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fcmp.h")
+
+
+@pytest.fixture(scope="module")
+def fc():
+    import paper_1205_4139_amd as fc
+    return fc
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcmp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(fc):
+    names = declared()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(fc.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_abi_version_and_status(fc):
+    assert fc.lib.fcmp_abi_version() == 1
+    assert fc.lib.fcmp_status_str(0) == b"ok"
+    assert fc.lib.fcmp_status_str(-2) == b"workspace too small"
+
+
+def _q(fc, cls="F", N=1024, M=256, K=16, omega=None, **opt):
+    om = (np.arange(M) * (N // max(M, 1))) if omega is None else omega
+    return fc.query_workspace(cls, N, M, K, om, **opt)
+
+
+def test_query_workspace_sizes(fc):
+    a = _q(fc)
+    b = _q(fc, K=32)
+    c = _q(fc, precision="fp32")
+    assert a > 0 and b > a and c > 0
+    big = _q(fc, N=1 << 20, M=1 << 17, K=1024, cls="H")
+    assert big > 1 << 24
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(N=1000, M=250), "power of two"),
+    (dict(N=1 << 25, M=256), "power of two"),
+    (dict(cls="F", N=1 << 23, M=256), "Fourier N"),
+    (dict(K=256), "K must be"),
+    (dict(K=0), "K must be"),
+    (dict(M=0, K=1), "M must be"),
+    (dict(omega=np.array([3, 2] + list(range(10, 264)))), "strictly increasing"),
+    (dict(omega=np.arange(256) + 900), "out of"),
+    (dict(method="bogus"), "corr_method"),
+])
+def test_validation_errors(fc, kw, msg):
+    with pytest.raises(fc.FcmpError) as ei:
+        if kw.get("method") == "bogus":
+            kw = dict(kw, method=7)
+        _q(fc, **kw)
+    assert ei.value.code == fc.E_INVALID
+    assert msg in str(ei.value)
+
+
+def test_solve_rejects_null_pointers_without_device(fc):
+    p, om = fc.make_problem("H", 1024, 256, 16, np.arange(256) * 4)
+    o = fc.make_options()
+    rc = fc.lib.fcmp_solve(ctypes.byref(p), ctypes.byref(o), None, None, 0, None, None, None, None)
+    assert rc == fc.E_INVALID
+    assert b"NULL" in fc.lib.fcmp_last_error()
+
+
+def test_plan_requires_one_shape(fc):
+    probs = (fc.Problem * 2)()
+    oms = [np.arange(256, dtype=np.int32) * 4, np.arange(128, dtype=np.int32) * 8]
+    for i, (M, om) in enumerate(zip((256, 128), oms)):
+        probs[i] = fc.Problem(0, 0, 1024, M, 16, om.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    o = fc.make_options()
+    n = ctypes.c_size_t(0)
+    rc = fc.lib.fcmp_plan_query_workspace(2, probs, ctypes.byref(o), ctypes.byref(n))
+    assert rc == fc.E_INVALID
+    rc = fc.lib.fcmp_batch_query_workspace(2, probs, ctypes.byref(o), ctypes.byref(n))
+    assert rc == 0 and n.value > 0
+
+
+def test_options_validation(fc):
+    with pytest.raises(fc.FcmpError):
+        _q(fc, precision=5)
+    p, om = fc.make_problem("H", 1024, 256, 16, np.arange(256) * 4)
+    o = fc.make_options()
+    o.flags = 8
+    n = ctypes.c_size_t(0)
+    assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID

@@ -68,3 +68,30 @@ def test_omp_parity(fc, case, method, precision):
         assert abs(res.stats.res_norm ** 2 - ref.res_norm ** 2) <= 1e-12 * np.linalg.norm(y) ** 2
         checked += 1
     assert checked >= 1
+
+
+LONG_CASES = [
+    ("F", 32768, 4096, 100, "cgauss", 30.0),    # odd log2 N: separate output grouping
+    ("H", 65536, 8192, 100, "pm_u12", None),    # Hadamard: contiguous output groups
+    ("F", 16384, 4096, 150, "cgauss", 30.0),
+]
+
+
+@pytest.mark.parametrize("resid", ["transform", "direct"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", LONG_CASES, ids=lambda c: f"{c[0]}{c[1]}-{c[3]}")
+def test_omp_long_support_residual_paths(fc, case, precision, resid, monkeypatch):
+    """Supports long enough for the split least-squares update (t > 64); the
+    residual is forced through the forward transform or the direct sum."""
+    monkeypatch.setenv("FCMP_RESID_RATIO", "0" if resid == "transform" else "1e30")
+    checked = 0
+    for seed in range(2):
+        inst, y, ref = _reference(case, 7100 + seed)
+        if not certify.certified(ref, precision):
+            continue
+        res = fc.solve(inst.cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y),
+                       method="conventional", precision=precision)
+        assert list(to_np(res.support)) == list(ref.support)
+        assert np.linalg.norm(to_np(res.x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+        checked += 1
+    assert checked >= 1

@@ -149,6 +149,25 @@ hipError_t launch_gather_ptr(int vk, const void* const* ptrs, const int32_t* idx
 hipError_t launch_finalize_ptr(int fourier, const Status* status, const int32_t* lam,
                                const void* x, int K, int64_t inst_lam, int64_t inst_x,
                                int32_t* const* sup, void* const* xo, int ninst, hipStream_t st);
+// top-K by |v|^2 (ties to the lowest index), excluded entries skipped;
+// out: K ascending indices (fewer when fewer entries are eligible: then the
+// state flag st[4] is set and the tail is unspecified).
+size_t topk_workspace(int64_t n);
+hipError_t launch_topk(const void* v, int kind, int64_t n, const uint32_t* excl, int64_t K,
+                       void* ws, int32_t* out, hipStream_t st);
+// Dense FP64 least squares on the support T (s ascending columns):
+// x = (Phi_T^H Phi_T)^{-1} Phi_T^H y from the kernel vector and h_0 by a
+// blocked Cholesky; *bad (device int) set to 1 on a non-positive pivot.
+size_t dense_ls_workspace(int s_max, bool fourier);
+hipError_t launch_dense_ls(int fourier, const void* c64, const void* h0, const int32_t* T, int s,
+                           int N, void* ws, void* x, int* bad, hipStream_t st);
+hipError_t launch_set_bits(uint32_t* bm, int64_t nwords, const int32_t* idx, int n,
+                           hipStream_t st);
+// per workgroup w: out[2w] = part of Re(h0(S)^H a), out[2w+1] = part of
+// Re(a^H G_S a) (squared residual norm pieces); set_quad_groups(s) workgroups
+int set_quad_groups(int s);
+hipError_t launch_set_quad(int fourier, const void* c64, const void* h0, const int32_t* S,
+                           const void* a, int s, int N, double* out, hipStream_t st);
 hipError_t launch_noise(int fourier, const void* clean, const void* noise, double snr_db,
                         void* y, int M, hipStream_t st);
 

@@ -29,7 +29,8 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
   }
   int rc = validate_options(&probs[0], opt);
   if (rc) return rc;
-  if (opt->algorithm != FCMP_OMP) return set_error(FCMP_E_INVALID, "algorithm not available");
+  if (opt->algorithm != FCMP_OMP && probs[0].K > 2048)
+    return set_error(FCMP_E_INVALID, "SP and CoSaMP support K <= 2048");
   P.n = n;
   P.shape = probs[0];
   P.shape.omega = nullptr;
@@ -89,6 +90,22 @@ void plan_layout(fcmp_plan& P, char* base) {
   P.wbuf = cv.take_bytes(n * P.sK * wb);
   P.vpart = cv.take_bytes(n * 16 * P.sK * wb);
   P.status = cv.take<Status>(n);
+  if (P.opt.algorithm != FCMP_OMP) {
+    const int64_t K = P.shape.K, N = P.shape.N;
+    const int smax = (int)(P.opt.algorithm == FCMP_SP ? 2 * K : 3 * K);
+    P.hbuf = cv.take_bytes(N * wb);
+    P.Ta = cv.take<int32_t>(3 * K);
+    P.Tb = cv.take<int32_t>(3 * K);
+    P.Tc = cv.take<int32_t>(3 * K);
+    P.Td = cv.take<int32_t>(3 * K);
+    P.xa = cv.take_bytes(3 * K * wb);
+    P.xb = cv.take_bytes(3 * K * wb);
+    P.xc = cv.take_bytes(3 * K * wb);
+    P.dws = cv.take_bytes(dense_ls_workspace(smax, P.wk == V_C128));
+    P.tkws = cv.take_bytes(topk_workspace(N));
+    P.small = cv.take<double>(256);
+    P.bad = cv.take<int>(16);
+  }
   P.dptrs = cv.take<void*>(3 * n);
   P.total = cv.total();
 }
@@ -213,6 +230,12 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
     d.scale = inv_sqrt_n;
     HIP_TRY(run_transform(P.wk, +1, g, tw_for(P, P.wk), en, XSrc{IN_SPARSE, P.wk, P.y_ent}, d,
                           P.tmp, nullptr, st, n, P.sN, P.sM, P.sP, P.sE, P.sG));
+  }
+  if (P.opt.algorithm != FCMP_OMP) {
+    rc = plan_solve_set(P, opt, (int32_t* const*)sup, xo, stats, st);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    return rc;
   }
   LParams lp{};
   lp.N = N; lp.fourier = F;

@@ -40,6 +40,19 @@ struct fcmp_plan {
   void* wbuf = nullptr;        // split least squares: w and the partial rows
   void* vpart = nullptr;
   fcmp::Status* status = nullptr;
+  // set-based pursuits (SP, CoSaMP), one instance at a time
+  void* hbuf = nullptr;        // N correlation values (FP64-sized)
+  int32_t* Ta = nullptr;       // index lists of up to 3K entries
+  int32_t* Tb = nullptr;
+  int32_t* Tc = nullptr;
+  int32_t* Td = nullptr;
+  void* xa = nullptr;          // coefficient lists of up to 3K FP64 values
+  void* xb = nullptr;
+  void* xc = nullptr;
+  void* dws = nullptr;         // dense least-squares workspace
+  void* tkws = nullptr;        // top-K workspace
+  double* small = nullptr;     // partial sums read back by the host
+  int* bad = nullptr;          // Cholesky breakdown flag
   void** dptrs = nullptr;      // 3n device pointers: y, support, x
   std::vector<const void*> last_ptrs;
   size_t total = 0;
@@ -54,5 +67,8 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st);
 int plan_solve(fcmp_plan& P, const fcmp_options* opt, const void* const* y,
                int32_t* const* sup, void* const* x, fcmp_stats* stats, hipStream_t st);
 int plan_kernel_vector(fcmp_plan& P, hipStream_t st);
+// SP / CoSaMP for every instance of the plan (after h_0 is in place)
+int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, void* const* xo,
+                   fcmp_stats* stats, hipStream_t st);
 
 }  // namespace fcmp

@@ -189,3 +189,67 @@ hipError_t launch_finalize_ptr(int fourier, const Status* status, const int32_t*
 }
 
 }  // namespace fcmp
+
+namespace fcmp {
+
+// bits of the listed columns set in an N-bit map (map cleared first by the caller)
+__global__ void set_bits_kernel(uint32_t* bm, const int32_t* idx, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t j = (uint32_t)idx[i];
+    atomicOr(&bm[j >> 5], 1u << (j & 31));
+  }
+}
+
+hipError_t launch_set_bits(uint32_t* bm, int64_t nwords, const int32_t* idx, int n,
+                           hipStream_t st) {
+  hipError_t e = launch_fill_u32(bm, 0u, nwords, st);
+  if (e != hipSuccess || n <= 0) return e;
+  hipLaunchKernelGGL(set_bits_kernel, dim3((n + 255) / 256), dim3(256), 0, st, bm, idx, n);
+  return hipGetLastError();
+}
+
+// out[0] = Re(sum_i conj(h0[S_i]) a_i), out[1] = Re(a^H G_S a) with
+// G_S[i][j] = c(S_i (-) S_j)   (one workgroup)
+template <class Wd, bool FOURIER>
+__global__ void set_quad_kernel(const Wd* c64, const Wd* h0, const int32_t* S, const Wd* a,
+                                int s, int N, double* out) {
+  __shared__ double red[16];
+  const uint32_t mask = (uint32_t)N - 1u;
+  double lin = 0.0, quad = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < s; i += gridDim.x * blockDim.x) {
+    const Wd ai = a[i];
+    const Wd hi = h0[S[i]];
+    Wd g = vzero(Wd());
+    for (int j = 0; j < s; ++j) {
+      const Wd cij = c64[perm_index(FOURIER, (uint32_t)S[i], (uint32_t)S[j], mask)];
+      if constexpr (FOURIER) { const double2 t = cmul(cij, a[j]); g.x += t.x; g.y += t.y; }
+      else g += cij * a[j];
+    }
+    if constexpr (FOURIER) {
+      lin += hi.x * ai.x + hi.y * ai.y;
+      quad += ai.x * g.x + ai.y * g.y;
+    } else {
+      lin += hi * ai;
+      quad += ai * g;
+    }
+  }
+  lin = block_sum(lin, red);
+  quad = block_sum(quad, red);
+  if (threadIdx.x == 0) { out[2 * blockIdx.x] = lin; out[2 * blockIdx.x + 1] = quad; }
+}
+
+int set_quad_groups(int s) { return std::max(1, std::min(64, (s + 255) / 256)); }
+
+hipError_t launch_set_quad(int fourier, const void* c64, const void* h0, const int32_t* S,
+                           const void* a, int s, int N, double* out, hipStream_t st) {
+  const int g = set_quad_groups(s);
+  if (fourier)
+    hipLaunchKernelGGL((set_quad_kernel<double2, true>), dim3(g), dim3(256), 0, st,
+                       (const double2*)c64, (const double2*)h0, S, (const double2*)a, s, N, out);
+  else
+    hipLaunchKernelGGL((set_quad_kernel<double, false>), dim3(g), dim3(256), 0, st,
+                       (const double*)c64, (const double*)h0, S, (const double*)a, s, N, out);
+  return hipGetLastError();
+}
+
+}  // namespace fcmp

@@ -106,6 +106,9 @@ typedef struct {
 /* fcmp_plan_solve recomputes the kernel vector (A1) instead of reusing the
  * one the plan stored at creation. */
 #define FCMP_FLAG_RECOMPUTE_KERNEL 1u
+/* fcmp_batch_solve runs every problem as a lockstep plan, never in the
+ * persistent one-workgroup-per-problem kernel. */
+#define FCMP_FLAG_NO_PERSISTENT 2u
 
 typedef struct {
   int32_t iterations;        /* OMP: selections made; SP/CoSaMP: outer iterations */
@@ -136,10 +139,13 @@ int fcmp_solve(const fcmp_problem* prob, const fcmp_options* opt,
                int32_t* support_dev, void* x_dev, fcmp_stats* stats,
                void* hip_stream);
 
-/* Many independent problems in one call.  Problems of one shape run in
- * lockstep; problems small enough for one workgroup's LDS run whole solves
- * per workgroup in one persistent launch.  Arrays are HOST arrays of n
- * entries holding device pointers; stats (nullable) is a host array of n. */
+/* Many independent problems in one call.  OMP problems whose transform fits
+ * one workgroup's LDS (N * element size <= 140 KiB, K <= 1024) run whole
+ * solves, one workgroup per problem, in one persistent launch after a
+ * lockstep prologue (kernel vector and h_0 per (class, N, M) group); the
+ * others run as lockstep plans per shape.  Arrays are HOST arrays of n
+ * entries holding device pointers; stats (nullable) is a host array of n
+ * (when given the call synchronises the stream). */
 int fcmp_batch_query_workspace(int64_t n, const fcmp_problem* probs,
                                const fcmp_options* opt, size_t* bytes);
 int fcmp_batch_solve(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,

@@ -341,8 +341,11 @@ def profile_read(reset=True) -> dict:
     return {name: (pr.ms[i], int(pr.launches[i])) for i, name in enumerate(PHASES)}
 
 
+FLAG_NO_PERSISTENT = 2
+
+
 def batch_solve(problems, ys, algorithm="omp", method="conventional", precision="fp64",
-                switch_t=0, device="cuda"):
+                switch_t=0, device="cuda", flags=0, stats=True):
     """Mixed-shape batch.  problems: list of (cls, N, M, K, omega); ys: list of
     device tensors.  Returns (supports, xs, stats) as lists."""
     torch = _torch()
@@ -352,14 +355,14 @@ def batch_solve(problems, ys, algorithm="omp", method="conventional", precision=
     for i, (cls, N, M, K, _o) in enumerate(problems):
         probs[i] = Problem(CLASS[cls], 0, int(N), int(M), int(K),
                            oms[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
-    o = make_options(algorithm, method, precision, 0, switch_t)
+    o = make_options(algorithm, method, precision, 0, switch_t, flags)
     nb = ctypes.c_size_t(0)
     _check(lib.fcmp_batch_query_workspace(n, probs, ctypes.byref(o), ctypes.byref(nb)))
     ws = _workspace(nb.value, device)
     sups = [torch.empty(int(p[3]), dtype=torch.int32, device=device) for p in problems]
     xs = [torch.empty(int(p[3]), dtype=_dtype(p[0]), device=device) for p in problems]
-    st = (Stats * n)()
+    st = (Stats * n)() if stats else None
     _check(lib.fcmp_batch_solve(n, probs, ctypes.byref(o), _ptr_array([y.data_ptr() for y in ys]),
                                 _ptr(ws), ws.numel(), _ptr_array([t.data_ptr() for t in sups]),
                                 _ptr_array([t.data_ptr() for t in xs]), st, _stream()))
-    return sups, xs, list(st)
+    return sups, xs, (list(st) if stats else None)

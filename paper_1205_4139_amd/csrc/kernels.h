@@ -168,6 +168,41 @@ hipError_t launch_set_bits(uint32_t* bm, int64_t nwords, const int32_t* idx, int
 int set_quad_groups(int s);
 hipError_t launch_set_quad(int fourier, const void* c64, const void* h0, const int32_t* S,
                            const void* a, int s, int N, double* out, hipStream_t st);
+// ------------------------------------------------------------------ persistent batch
+// One workgroup runs a whole OMP solve of one instance (N small enough for
+// its transform tile to live in LDS); workgroups pull instances from an
+// atomic counter in the order given by `order` (largest first).
+struct WgDesc {
+  int32_t cls;            // FCMP_HADAMARD / FCMP_FOURIER
+  int32_t N, logN, M, K;
+  int32_t method;         // FCMP_CORR_*
+  int32_t switch_t;       // adaptive: last iteration with the fast method
+  int32_t pad;
+  int64_t off_om;         // int32[M]   rows of Phi (any order, matching off_y)
+  int64_t off_y;          // FP64[M]
+  int64_t off_c64;        // FP64[N]    kernel vector
+  int64_t off_cp;         // corr[N]    kernel vector in the correlation precision
+  int64_t off_h0;         // FP64[N]
+  int64_t off_W;          // FP64[K(K+1)/2]
+  int64_t off_x, off_z;   // FP64[K]
+  int32_t* sup_out;       // caller's support (K)
+  void* x_out;            // caller's x (K)
+};
+struct WgParams {
+  const WgDesc* desc;
+  const int32_t* order;
+  int n;
+  int* counter;           // zeroed before the launch
+  char* base;             // workspace base for the offsets
+  Status* status;         // per instance (indexed like desc)
+  const double2* tw64;    // two-level twiddles for Nmax, sign +
+  const float2* tw32;
+  int logNmax, twS;
+  int Kmax;
+  size_t tile_bytes;      // LDS bytes reserved for the transform tile
+};
+hipError_t launch_omp_wg(const WgParams& p, int precision, int groups, hipStream_t st);
+size_t omp_wg_lds_bytes(const WgParams& p);
 hipError_t launch_noise(int fourier, const void* clean, const void* noise, double snr_db,
                         void* y, int M, hipStream_t st);
 

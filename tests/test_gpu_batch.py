@@ -86,3 +86,52 @@ def test_mixed_batch_solve(fc):
             assert list(to_np(sups[i])) == list(ref.support)
             assert np.linalg.norm(to_np(xs[i]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
         assert stats[i].iterations == probs[i][3]
+
+
+_UNEVEN = {}
+
+
+def _uneven(count, seed, logn=(10, 13), snr=40.0):
+    key = (count, seed, logn, snr)
+    if key not in _UNEVEN:
+        insts = instancegen.draw_batch(count, seed, logn_range=logn, snr_db=snr)
+        ys = [oracle.problem.instance_measure(i, tier="transform") for i in insts]
+        refs = [oracle.omp(oracle.make_operator(i.cls, i.N, i.omega), y, i.K)
+                for i, y in zip(insts, ys)]
+        _UNEVEN[key] = (insts, ys, refs)
+    return _UNEVEN[key]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["conventional", "fast", "adaptive"])
+def test_persistent_batch_matches_oracle_and_alone(fc, method, precision):
+    """The persistent one-workgroup-per-instance path: every instance agrees
+    with the oracle (certified instances) and is bit-identical when solved
+    alone."""
+    insts, ys, refs = _uneven(24, 8400)
+    probs = [(i.cls, i.N, i.M, i.K, i.omega) for i in insts]
+    sups, xs, stats = fc.batch_solve(probs, [to_dev(y) for y in ys], method=method,
+                                     precision=precision)
+    checked = 0
+    for k, (inst, y, ref) in enumerate(zip(insts, ys, refs)):
+        assert stats[k].iterations == inst.K
+        if certify.certified(ref, precision):
+            assert list(to_np(sups[k])) == list(ref.support)
+            assert np.linalg.norm(to_np(xs[k]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+            checked += 1
+    assert checked >= 12
+    for k in (0, 5, 17):
+        s1, x1, _ = fc.batch_solve([probs[k]], [to_dev(ys[k])], method=method, precision=precision)
+        assert np.array_equal(to_np(s1[0]), to_np(sups[k]))
+        assert np.array_equal(to_np(x1[0]), to_np(xs[k]))
+
+
+def test_persistent_and_lockstep_agree(fc):
+    insts, ys, _ = _uneven(10, 8500)
+    probs = [(i.cls, i.N, i.M, i.K, i.omega) for i in insts]
+    yd = [to_dev(y) for y in ys]
+    a = fc.batch_solve(probs, yd, precision="fp64")
+    b = fc.batch_solve(probs, yd, precision="fp64", flags=fc.FLAG_NO_PERSISTENT)
+    for k in range(len(insts)):
+        assert np.array_equal(to_np(a[0][k]), to_np(b[0][k]))
+        assert np.allclose(to_np(a[1][k]), to_np(b[1][k]), rtol=0, atol=1e-12 * np.abs(to_np(b[1][k])).max())

@@ -124,6 +124,106 @@ def cpu_baseline(inst, iters: int):
     }
 
 
+def measure_host(fc, inst, device):
+    """y = Phi x + noise for one instance, computed on the device, as a host array."""
+    import numpy as np
+    import torch
+    x = torch.from_numpy(inst.x_dense()).to(device)
+    g = torch.from_numpy(np.ascontiguousarray(inst.noise)).to(device)
+    return fc.measure(inst.cls, inst.N, inst.omega, x, g, inst.snr_db)
+
+
+def batch_leg(fc, device, count: int, steps: int, plain_n: int):
+    """Uneven batch: `count` instances, F for even i else H, N = 2^U{10..14},
+    M = N/4, K ~ U{8..M/8}, 40 dB; complex64 / FP32 correlation, FP64 LS; one
+    batch plan (persistent launch, graph-captured), against plain
+    single-instance fcmp_solve calls on a sample of the same instances."""
+    import numpy as np
+    import torch
+
+    import instancegen
+    insts = instancegen.draw_batch(count, 4000)
+    ys = [measure_host(fc, i, device) for i in insts]
+    torch.cuda.synchronize()
+    probs = [(i.cls, i.N, i.M, i.K, i.omega) for i in insts]
+    t0 = time.perf_counter()
+    bp = fc.BatchPlan(probs, method="conventional", precision="fp32", device=device)
+    t_create = time.perf_counter() - t0
+    bp.solve(ys)
+    torch.cuda.synchronize()
+    t = time_steps(lambda: bp.solve(ys), steps, 0)
+    sup, _x, st = bp.solve(ys, stats=True)
+    done_ms = np.array([s.ms_total for s in st])
+    rec = float(np.mean([set(sup[k].cpu().numpy()) == set(insts[k].support)
+                         for k in range(count)]))
+    bp.close()
+    lat = []
+    idx = np.linspace(0, count - 1, plain_n).astype(int)
+    for k in idx:
+        i = insts[k]
+        t1 = time.perf_counter()
+        fc.solve(i.cls, i.N, i.M, i.K, i.omega, ys[k], precision="fp32", stats=True)
+        lat.append(time.perf_counter() - t1)
+    lat = np.array(lat) * 1e3
+    return {
+        "workload": f"{count} uneven OMP instances: F (even i) / H, N = 2^U{{10..14}}, M = N/4, "
+                    "K ~ U{8..M/8}, 40 dB, complex64/FP32 correlation + FP64 LS",
+        "solves_per_s": round(count / t, 1),
+        "ms_per_batch": round(t * 1e3, 3),
+        "completion_ms": {"p50": round(float(np.percentile(done_ms, 50)), 3),
+                          "p99": round(float(np.percentile(done_ms, 99)), 3),
+                          "max": round(float(done_ms.max()), 3)},
+        "plan_create_ms": round(t_create * 1e3, 1),
+        "support_recovery_rate": rec,
+        "plain": {"solves_per_s": round(1e3 / float(lat.mean()), 2),
+                  "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                  "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                  "sample": f"{plain_n} instances spread over the batch, fcmp_solve each"},
+        "speedup_vs_plain": round((count / t) / (1e3 / float(lat.mean())), 1),
+    }
+
+
+def serve_leg(fc, device, count: int, rate_hz: float):
+    """Poisson request stream (rate_hz), class ~ Bernoulli(1/2), log2 N ~
+    U{12..18}, M ~ U{N/8..N/4}, K ~ U{16..M/16}, 30 dB, complex64/FP32
+    correlation; requests submitted at their arrival times to the
+    continuous-batching server; latency = done - submit."""
+    import numpy as np
+    import torch
+
+    import instancegen
+    arr, insts = instancegen.draw_stream(count, seed=5000, rate_hz=rate_hz)
+    ys = [measure_host(fc, i, device).cpu().numpy() for i in insts]
+    srv = fc.Server(64 << 30, device=device)
+    t0 = time.perf_counter()
+    tickets = []
+    for a, i, y in zip(arr, insts, ys):
+        while time.perf_counter() - t0 < a:
+            pass
+        tickets.append(srv.submit(i.cls, i.N, i.M, i.K, i.omega, y, precision="fp32"))
+    t_sub = time.perf_counter() - t0
+    srv.drain(0)
+    res = [srv.poll(t) for t in tickets]
+    info = srv.info()
+    srv.close()
+    sub = np.array([r["times"][0] for r in res])
+    done = np.array([r["times"][2] for r in res])
+    lat = done - sub
+    span = (done.max() - sub.min()) / 1e3
+    rec = float(np.mean([set(r["support"]) == set(i.support) for r, i in zip(res, insts)]))
+    return {
+        "workload": f"{count}-request Poisson stream at {rate_hz:.0f} req/s: F/H, N = 2^U{{12..18}}, "
+                    "M ~ U{N/8..N/4}, K ~ U{16..M/16}, 30 dB, complex64/FP32 correlation",
+        "offered_req_per_s": round(count / max(t_sub, 1e-9), 1),
+        "completed_req_per_s": round(count / span, 1),
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
+                       "p99": round(float(np.percentile(lat, 99)), 2)},
+        "waves": int(info["waves"]),
+        "pool_peak_GiB": round(info["pool_peak"] / 2**30, 2),
+        "support_recovery_rate": rec,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +234,9 @@ def main():
     ap.add_argument("--plain", type=int, default=6, help="single-instance solves to time")
     ap.add_argument("--cpu-iters", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20000.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -204,6 +307,14 @@ def main():
              "note": "fcmp_solve: one instance per call, kernel vector included, host-synchronised"}
     print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
 
+    batch = serve = None
+    if args.batch_count > 0:
+        batch = batch_leg(fc, dev, args.batch_count, max(args.steps, 3), 48)
+        print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
+    if args.serve_requests > 0:
+        serve = serve_leg(fc, dev, args.serve_requests, args.serve_rate)
+        print(f"[bench] serve: {serve}", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -228,6 +339,8 @@ def main():
         "methods": methods,
         "support_recovery_rate": recovered,
         "phases": phases,
+        "uneven_batch": batch,
+        "serving": serve,
         "roofline": {
             "kernel": "conventional correlation (xform pass 1 + pass 2, complex64, B instances)",
             "bound": "hbm",

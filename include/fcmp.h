@@ -114,7 +114,9 @@ typedef struct {
   int32_t iterations;        /* OMP: selections made; SP/CoSaMP: outer iterations */
   int32_t status;            /* FCMP_OK or FCMP_E_NUMERIC */
   double  res_norm;          /* ||y - Phi_Lambda x|| (from the normal equations) */
-  double  ms_total;          /* device time of the solve (hipEvent), ms */
+  double  ms_total;          /* device time of the solve (hipEvent), ms; for a
+                                problem run by the persistent batch kernel: its
+                                completion time from the start of the batch */
 } fcmp_stats;
 
 int         fcmp_abi_version(void);
@@ -153,6 +155,28 @@ int fcmp_batch_solve(int64_t n, const fcmp_problem* probs, const fcmp_options* o
                      int32_t* const* support_dev, void* const* x_dev,
                      fcmp_stats* stats, void* hip_stream);
 
+/* A batch plan fixes a set of n uneven problems (each with its own Omega and
+ * shape; one options record): creation builds every table, descriptor and
+ * kernel vector once and, for OMP, captures the whole device work of a
+ * solve -- the persistent launch with its prologue and every lockstep plan's
+ * iterations -- into one hipGraph.  Each fcmp_batch_plan_solve uploads the
+ * n (y, support, x) device pointers and replays the graph on the caller's
+ * stream.  SP/CoSaMP batch plans run eagerly (their loops read partial
+ * results back on the host).  The workspace (from
+ * fcmp_batch_plan_query_workspace, host-only) must stay untouched while the
+ * plan lives; solves on one plan must not overlap.  Creation synchronises
+ * the stream.  Pointer arrays and stats are as for fcmp_batch_solve. */
+typedef struct fcmp_batch_plan fcmp_batch_plan;
+int fcmp_batch_plan_query_workspace(int64_t n, const fcmp_problem* probs,
+                                    const fcmp_options* opt, size_t* bytes);
+int fcmp_batch_plan_create(fcmp_batch_plan** out, int64_t n, const fcmp_problem* probs,
+                           const fcmp_options* opt, void* ws_dev, size_t ws_bytes,
+                           void* hip_stream);
+int fcmp_batch_plan_solve(fcmp_batch_plan* plan, const void* const* y_dev,
+                          int32_t* const* support_dev, void* const* x_dev,
+                          fcmp_stats* stats, void* hip_stream);
+int fcmp_batch_plan_destroy(fcmp_batch_plan* plan);
+
 /* ---- plans ------------------------------------------------------------ */
 
 /* A plan holds, in the caller's device workspace, what depends on Omega only
@@ -178,6 +202,68 @@ int fcmp_plan_solve(fcmp_plan* plan, const fcmp_options* opt, const void* const*
                     int32_t* const* support_dev, void* const* x_dev, fcmp_stats* stats,
                     void* hip_stream);
 int fcmp_plan_destroy(fcmp_plan* plan);
+
+/* ---- serving ---------------------------------------------------------- */
+
+/* A solver service with continuous batching.  Requests (problem, options,
+ * y on the HOST) queue on submit; worker threads, one per HIP stream the
+ * server creates (default priority), admit them in arrival order whenever
+ * request slots and room in the caller's device pool allow, and run them as
+ * waves: all queued OMP requests the persistent one-workgroup-per-problem
+ * kernel takes, with the same options, in one persistent launch (at most
+ * max_wave); any other request as a lockstep plan with the queued requests
+ * of its shape.  With several streams, stream 0 runs persistent waves only.
+ * Waves on different
+ * streams overlap on the device.  A request's device state stays in its
+ * wave's pool region from admission to completion; results are copied to
+ * host memory and the region is returned to the pool.  A request's results
+ * do not depend on which other requests it shared a wave with.
+ * The library never allocates device memory beyond the pool (pinned host
+ * staging is allocated per worker). */
+typedef struct fcmp_server fcmp_server;
+typedef struct {
+  int32_t max_slots;         /* requests on the device at once (0: 4096) */
+  int32_t max_pending;       /* queued, not yet admitted (0: 65536); more: FCMP_E_BUSY */
+  int32_t n_streams;         /* worker streams, 1..8 (0: 4) */
+  int32_t max_wave;          /* requests per persistent wave (0: 1024) */
+} fcmp_server_config;
+typedef struct {             /* milliseconds on the server's clock (from creation) */
+  double t_submit;           /* fcmp_server_submit returned the ticket */
+  double t_launch;           /* admitted: its wave started */
+  double t_done;             /* results were back in host memory */
+} fcmp_times;
+typedef struct {
+  int64_t submitted, completed, queued, inflight, waves;
+  int64_t pool_peak;         /* most pool bytes in use at once */
+} fcmp_server_info;
+
+/* Device pool bytes one request occupies when admitted alone (solver state
+ * plus y, support and x); the admission test uses it.  Host-only. */
+int fcmp_server_footprint(const fcmp_problem* prob, const fcmp_options* opt, size_t* bytes);
+/* pool_dev / pool_bytes: caller-owned device memory, untouched by anything
+ * else while the server lives.  cfg nullable (all defaults).  The current
+ * device at creation is the server's device. */
+int fcmp_server_create(fcmp_server** out, void* pool_dev, size_t pool_bytes,
+                       const fcmp_server_config* cfg);
+/* y_host: M values (float64 | complex128), copied before the call returns;
+ * omega is copied too.  FCMP_E_WORKSPACE when the request can never fit the
+ * pool, FCMP_E_BUSY when max_pending requests are queued. */
+int fcmp_server_submit(fcmp_server* srv, const fcmp_problem* prob, const fcmp_options* opt,
+                       const void* y_host, uint64_t* ticket);
+/* Non-blocking.  *done = 0 while the request runs.  Once done, copies K
+ * support entries and K values of x to the host buffers (each nullable),
+ * fills stats and times (nullable; stats.ms_total is the completion time
+ * from the wave's start), forgets the ticket and returns the request's
+ * status (FCMP_E_NOTFOUND for an unknown or already collected ticket). */
+int fcmp_server_poll(fcmp_server* srv, uint64_t ticket, int32_t* support_host, void* x_host,
+                     fcmp_stats* stats, fcmp_times* times, int32_t* done);
+/* Waits until no request is queued or running (timeout_ms <= 0: no limit);
+ * FCMP_E_BUSY at the timeout. */
+int fcmp_server_drain(fcmp_server* srv, double timeout_ms);
+int fcmp_server_get_info(fcmp_server* srv, fcmp_server_info* info);
+/* Finishes the running waves, drops queued requests and frees the host
+ * objects; the pool may be reused once it returns. */
+int fcmp_server_destroy(fcmp_server* srv);
 
 /* ---- phase timing ------------------------------------------------------ */
 

@@ -64,6 +64,22 @@ PHASES = ["kernel", "h0", "corr", "fast", "resid", "ls", "other"]
 FLAG_RECOMPUTE_KERNEL = 1
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("max_pending", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("max_wave", ctypes.c_int32)]
+
+
+class Times(ctypes.Structure):
+    _fields_ = [("t_submit", ctypes.c_double), ("t_launch", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("inflight", ctypes.c_int64),
+                ("waves", ctypes.c_int64), ("pool_peak", ctypes.c_int64)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * NPHASE), ("launches", ctypes.c_int64 * NPHASE)]
 
@@ -83,7 +99,21 @@ def _load():
         "fcmp_batch_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_batch_solve": ([i64, P, O, ctypes.POINTER(vp), vp, sz, ctypes.POINTER(vp),
                               ctypes.POINTER(vp), ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "fcmp_batch_plan_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_batch_plan_create": ([ctypes.POINTER(vp), i64, P, O, vp, sz, vp], ctypes.c_int),
+        "fcmp_batch_plan_solve": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "fcmp_batch_plan_destroy": ([vp], ctypes.c_int),
         "fcmp_plan_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_server_footprint": ([P, O, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_server_create": ([ctypes.POINTER(vp), vp, sz, ctypes.POINTER(ServerConfig)],
+                               ctypes.c_int),
+        "fcmp_server_submit": ([vp, P, O, vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "fcmp_server_poll": ([vp, ctypes.c_uint64, vp, vp, ctypes.POINTER(Stats),
+                             ctypes.POINTER(Times), ctypes.POINTER(i32)], ctypes.c_int),
+        "fcmp_server_drain": ([vp, dbl], ctypes.c_int),
+        "fcmp_server_get_info": ([vp, ctypes.POINTER(ServerInfo)], ctypes.c_int),
+        "fcmp_server_destroy": ([vp], ctypes.c_int),
         "fcmp_plan_create": ([ctypes.POINTER(vp), i64, P, O, vp, sz, vp], ctypes.c_int),
         "fcmp_plan_solve": ([vp, O, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                              ctypes.POINTER(Stats), vp], ctypes.c_int),
@@ -366,3 +396,123 @@ def batch_solve(problems, ys, algorithm="omp", method="conventional", precision=
                                 _ptr(ws), ws.numel(), _ptr_array([t.data_ptr() for t in sups]),
                                 _ptr_array([t.data_ptr() for t in xs]), st, _stream()))
     return sups, xs, (list(st) if stats else None)
+
+
+class BatchPlan:
+    """A fixed set of uneven problems, list of (cls, N, M, K, omega): tables and
+    kernel vectors built once; each solve replays one captured device graph
+    (OMP).  Outputs are lists of device tensors, overwritten by the next solve."""
+
+    def __init__(self, problems, algorithm="omp", method="conventional", precision="fp64",
+                 switch_t=0, flags=0, device="cuda"):
+        torch = _torch()
+        self.n = len(problems)
+        self.problems = problems
+        self._oms = [np.ascontiguousarray(np.asarray(p[4], dtype=np.int32)) for p in problems]
+        self._probs = (Problem * self.n)()
+        for i, (cls, N, M, K, _o) in enumerate(problems):
+            self._probs[i] = Problem(CLASS[cls], 0, int(N), int(M), int(K),
+                                     self._oms[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        self.opt = make_options(algorithm, method, precision, 0, switch_t, flags)
+        nb = ctypes.c_size_t(0)
+        _check(lib.fcmp_batch_plan_query_workspace(self.n, self._probs, ctypes.byref(self.opt),
+                                                   ctypes.byref(nb)))
+        self.ws_bytes = nb.value
+        self.ws = _workspace(nb.value, device)
+        self._h = ctypes.c_void_p(0)
+        _check(lib.fcmp_batch_plan_create(ctypes.byref(self._h), self.n, self._probs,
+                                          ctypes.byref(self.opt), _ptr(self.ws), self.ws.numel(),
+                                          _stream()))
+        self.support = [torch.empty(int(p[3]), dtype=torch.int32, device=device) for p in problems]
+        self.x = [torch.empty(int(p[3]), dtype=_dtype(p[0]), device=device) for p in problems]
+        self._sp = _ptr_array([t.data_ptr() for t in self.support])
+        self._xp = _ptr_array([t.data_ptr() for t in self.x])
+
+    def solve(self, ys, stats=False):
+        st = (Stats * self.n)() if stats else None
+        _check(lib.fcmp_batch_plan_solve(self._h, _ptr_array([y.data_ptr() for y in ys]),
+                                         self._sp, self._xp, st, _stream()))
+        return self.support, self.x, (list(st) if stats else None)
+
+    def close(self):
+        if self._h:
+            lib.fcmp_batch_plan_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def server_footprint(cls, N, M, K, omega, algorithm="omp", method="conventional",
+                     precision="fp64", switch_t=0, flags=0) -> int:
+    """Device pool bytes one request occupies when admitted alone (host-only)."""
+    prob, _keep = make_problem(cls, N, M, K, omega)
+    o = make_options(algorithm, method, precision, 0, switch_t, flags)
+    nb = ctypes.c_size_t(0)
+    _check(lib.fcmp_server_footprint(ctypes.byref(prob), ctypes.byref(o), ctypes.byref(nb)))
+    return nb.value
+
+
+class Server:
+    """Continuous-batching solver service over a device pool of pool_bytes.
+    submit() takes host arrays and returns a ticket; poll() returns None while
+    the request runs, else a dict with support, x, stats and times."""
+
+    def __init__(self, pool_bytes, max_slots=0, max_pending=0, n_streams=0, max_wave=0,
+                 device="cuda"):
+        self.pool = _workspace(int(pool_bytes), device)
+        cfg = ServerConfig(max_slots, max_pending, n_streams, max_wave)
+        self._h = ctypes.c_void_p(0)
+        _check(lib.fcmp_server_create(ctypes.byref(self._h), _ptr(self.pool), self.pool.numel(),
+                                      ctypes.byref(cfg)))
+        self._shapes = {}
+
+    def submit(self, cls, N, M, K, omega, y, algorithm="omp", method="conventional",
+               precision="fp64", switch_t=0, flags=0) -> int:
+        prob, _keep = make_problem(cls, N, M, K, omega)
+        o = make_options(algorithm, method, precision, 0, switch_t, flags)
+        yh = np.ascontiguousarray(np.asarray(y, dtype=np.complex128 if cls == "F" else np.float64))
+        if yh.shape != (int(M),):
+            raise ValueError("y must hold M values")
+        t = ctypes.c_uint64(0)
+        _check(lib.fcmp_server_submit(self._h, ctypes.byref(prob), ctypes.byref(o),
+                                      yh.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)))
+        self._shapes[t.value] = (cls, int(K))
+        return t.value
+
+    def poll(self, ticket):
+        cls, K = self._shapes[ticket]
+        sup = np.empty(K, dtype=np.int32)
+        x = np.empty(K, dtype=np.complex128 if cls == "F" else np.float64)
+        st, tm, done = Stats(), Times(), ctypes.c_int32(0)
+        rc = lib.fcmp_server_poll(self._h, ticket, sup.ctypes.data_as(ctypes.c_void_p),
+                                  x.ctypes.data_as(ctypes.c_void_p), ctypes.byref(st),
+                                  ctypes.byref(tm), ctypes.byref(done))
+        if rc == 0 and not done.value:
+            return None
+        del self._shapes[ticket]
+        _check(rc)
+        return {"support": sup, "x": x, "stats": st,
+                "times": (tm.t_submit, tm.t_launch, tm.t_done)}
+
+    def drain(self, timeout_ms=0.0):
+        _check(lib.fcmp_server_drain(self._h, float(timeout_ms)))
+
+    def info(self) -> dict:
+        i = ServerInfo()
+        _check(lib.fcmp_server_get_info(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _t in ServerInfo._fields_}
+
+    def close(self):
+        if self._h:
+            lib.fcmp_server_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -350,138 +350,4 @@ int fcmp_measure(const fcmp_problem* prob, const void* x_dev, const void* noise_
   return FCMP_OK;
 }
 
-static int batch_groups(int64_t n, const fcmp_problem* probs,
-                        std::vector<std::vector<int64_t>>& groups) {
-  if (n < 1 || !probs) return set_error(FCMP_E_INVALID, "empty batch");
-  std::map<std::tuple<int, int64_t, int64_t, int64_t>, size_t> idx;
-  for (int64_t b = 0; b < n; ++b) {
-    const auto key = std::make_tuple(probs[b].matrix_class, probs[b].N, probs[b].M, probs[b].K);
-    auto it = idx.find(key);
-    if (it == idx.end()) {
-      idx[key] = groups.size();
-      groups.push_back({b});
-    } else {
-      groups[it->second].push_back(b);
-    }
-  }
-  return FCMP_OK;
-}
-
-static void batch_split(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
-                        std::vector<int64_t>& wg, std::vector<int64_t>& rest) {
-  const bool allow = !(opt->flags & FCMP_FLAG_NO_PERSISTENT);
-  for (int64_t b = 0; b < n; ++b) {
-    if (allow && wg_eligible(probs[b], *opt)) wg.push_back(b);
-    else rest.push_back(b);
-  }
-}
-
-static int batch_sizes(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
-                       std::vector<int64_t>& wg, std::vector<int64_t>& rest, WgBatch& B,
-                       size_t* wg_bytes, size_t* rest_bytes) {
-  if (n < 1 || !probs) return set_error(FCMP_E_INVALID, "empty batch");
-  for (int64_t b = 0; b < n; ++b) {
-    int rc = validate_problem(&probs[b], true);
-    if (rc) return rc;
-    if ((rc = validate_options(&probs[b], opt))) return rc;
-  }
-  batch_split(n, probs, opt, wg, rest);
-  *wg_bytes = 0;
-  *rest_bytes = 0;
-  if (!wg.empty()) {
-    int rc = wg_plan_init(B, (int64_t)wg.size(), probs, wg.data(), opt);
-    if (rc) return rc;
-    *wg_bytes = B.total;
-  }
-  if (!rest.empty()) {
-    std::vector<fcmp_problem> sub;
-    for (int64_t b : rest) sub.push_back(probs[b]);
-    std::vector<std::vector<int64_t>> groups;
-    int rc = batch_groups((int64_t)sub.size(), sub.data(), groups);
-    if (rc) return rc;
-    for (const auto& gidx : groups) {
-      std::vector<fcmp_problem> g;
-      for (int64_t i : gidx) g.push_back(sub[i]);
-      fcmp_plan P;
-      if ((rc = plan_init(P, (int64_t)g.size(), g.data(), opt))) return rc;
-      *rest_bytes = std::max(*rest_bytes, P.total);
-    }
-  }
-  return FCMP_OK;
-}
-
-int fcmp_batch_query_workspace(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
-                               size_t* bytes) {
-  if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
-  if (!opt) return set_error(FCMP_E_INVALID, "options is NULL");
-  std::vector<int64_t> wg, rest;
-  WgBatch B;
-  size_t a = 0, b = 0;
-  int rc = batch_sizes(n, probs, opt, wg, rest, B, &a, &b);
-  if (rc) return rc;
-  *bytes = ((a + 255) & ~(size_t)255) + b;
-  return FCMP_OK;
-}
-
-int fcmp_batch_solve(int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
-                     const void* const* y_dev, void* ws_dev, size_t ws_bytes,
-                     int32_t* const* support_dev, void* const* x_dev, fcmp_stats* stats,
-                     void* hip_stream) {
-  if (!opt) return set_error(FCMP_E_INVALID, "options is NULL");
-  std::vector<int64_t> wg, rest;
-  WgBatch B;
-  size_t a = 0, b = 0;
-  int rc = batch_sizes(n, probs, opt, wg, rest, B, &a, &b);
-  if (rc) return rc;
-  const size_t a_pad = (a + 255) & ~(size_t)255;
-  if (!ws_dev) return set_error(FCMP_E_INVALID, "workspace is NULL");
-  if (ws_bytes < a_pad + b) return set_error(FCMP_E_WORKSPACE, "workspace too small");
-  if (!y_dev || !support_dev || !x_dev) return set_error(FCMP_E_INVALID, "NULL pointer array");
-  for (int64_t i = 0; i < n; ++i)
-    if (!y_dev[i] || !support_dev[i] || !x_dev[i])
-      return set_error(FCMP_E_INVALID, "NULL device pointer");
-  hipStream_t st = (hipStream_t)hip_stream;
-  int worst = FCMP_OK;
-  if (!wg.empty()) {
-    wg_layout(B, probs, (char*)ws_dev);
-    rc = wg_solve_batch(B, probs, y_dev, support_dev, x_dev, stats, st);
-    if (rc && rc != FCMP_E_NUMERIC) return rc;
-    if (rc) worst = rc;
-  }
-  if (!rest.empty()) {
-    std::vector<fcmp_problem> sub;
-    for (int64_t i : rest) sub.push_back(probs[i]);
-    std::vector<std::vector<int64_t>> groups;
-    batch_groups((int64_t)sub.size(), sub.data(), groups);
-    char* base = (char*)ws_dev + a_pad;
-    for (const auto& gidx : groups) {
-      std::vector<fcmp_problem> g;
-      std::vector<const void*> ys;
-      std::vector<int32_t*> ss;
-      std::vector<void*> xs;
-      std::vector<fcmp_stats> sts(gidx.size());
-      for (int64_t i : gidx) {
-        const int64_t orig = rest[i];
-        g.push_back(probs[orig]);
-        ys.push_back(y_dev[orig]);
-        ss.push_back(support_dev[orig]);
-        xs.push_back(x_dev[orig]);
-      }
-      fcmp_plan P;
-      if ((rc = plan_init(P, (int64_t)g.size(), g.data(), opt))) return rc;
-      plan_layout(P, base);
-      if ((rc = plan_build(P, g.data(), st))) return rc;
-      rc = plan_solve(P, nullptr, ys.data(), ss.data(), xs.data(), sts.data(), st);
-      if (rc && rc != FCMP_E_NUMERIC) return rc;
-      if (rc) worst = rc;
-      if (stats)
-        for (size_t i = 0; i < gidx.size(); ++i) stats[rest[gidx[i]]] = sts[i];
-    }
-  }
-  if (!stats) {
-    // the persistent path returns before the device is done; nothing to report
-  }
-  return worst;
-}
-
 }  // extern "C"

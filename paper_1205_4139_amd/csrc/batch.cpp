@@ -77,16 +77,16 @@ int wg_plan_init(WgBatch& B, int64_t n, const fcmp_problem* probs, const int64_t
 void wg_layout(WgBatch& B, const fcmp_problem* probs, char* base) {
   Carver cv;
   cv.base = base;
-  const int Nmax = 1 << B.logNmax;
-  const int twS = B.logNmax / 2;
-  const size_t ntw = ((size_t)1 << twS) + ((size_t)Nmax >> twS);
+  const int twS = WG_LOGT / 2;
+  const size_t ntw = ((size_t)1 << twS) + (((size_t)1 << WG_LOGT) >> twS);
   B.tw64 = cv.take<double2>(ntw);
   B.tw32 = cv.take<float2>(ntw);
   B.desc = cv.take<WgDesc>(B.n);
   B.order = cv.take<int32_t>(B.n);
   B.counter = cv.take<int>(16);
+  B.t0 = cv.take<uint64_t>(4);
   B.status = cv.take<Status>(B.n);
-  B.yptrs = cv.take<void*>(B.n);
+  B.ptrs = cv.take<void*>(3 * B.n);
   B.base = base;
   for (WgGroup& G : B.groups) {
     const bool F = G.cls == FCMP_FOURIER;
@@ -119,13 +119,33 @@ void wg_layout(WgBatch& B, const fcmp_problem* probs, char* base) {
   B.total = cv.total();
 }
 
+void wg_host_ptrs(const WgBatch& B, const void* const* y, int32_t* const* sup,
+                  void* const* xo, void** out) {
+  const int64_t n = B.n;
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t id = B.order_ids[q];
+    out[q] = const_cast<void*>(y[id]);
+    out[n + q] = sup[id];
+    out[2 * n + q] = xo[id];
+  }
+}
+
 int wg_solve_batch(WgBatch& B, const fcmp_problem* probs, const void* const* y,
                    int32_t* const* sup, void* const* xo, fcmp_stats* stats, hipStream_t st) {
+  int rc = wg_build(B, probs, st);
+  if (rc) return rc;
+  std::vector<void*> hp(3 * B.n);
+  wg_host_ptrs(B, y, sup, xo, hp.data());
+  HIP_TRY(hipMemcpyAsync(B.ptrs, hp.data(), hp.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return wg_run(B, stats, st);
+}
+
+int wg_build(WgBatch& B, const fcmp_problem* probs, hipStream_t st) {
   const int64_t n = B.n;
   char* base = B.base;
   // ---- host tables and descriptors
   std::vector<WgDesc> desc(n);
-  std::vector<const void*> yp(n);
   HostTables t;
   for (WgGroup& G : B.groups) {
     const int64_t c = G.count;
@@ -144,9 +164,9 @@ int wg_solve_batch(WgBatch& B, const fcmp_problem* probs, const void* const* y,
     HIP_TRY(hipMemcpyAsync(G.goff, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
-  // Nmax twiddles for the persistent kernel
+  // fixed-size twiddles for the persistent kernel
   {
-    Geo gm = make_geo(true, 1 << B.logNmax);
+    Geo gm = make_geo(true, 1 << WG_LOGT);
     build_tables(gm, nullptr, 0, t);
     HIP_TRY(hipMemcpyAsync(B.tw64, t.tw64.data(), t.tw64.size() * 16, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(B.tw32, t.tw32.data(), t.tw32.size() * 8, hipMemcpyHostToDevice, st));
@@ -178,9 +198,6 @@ int wg_solve_batch(WgBatch& B, const fcmp_problem* probs, const void* const* y,
       d.off_W = B.inst_off[q];
       d.off_x = d.off_W + (int64_t)((size_t)p.K * (p.K + 1) / 2 * wb);
       d.off_z = d.off_x + pad64(p.K) * (int64_t)wb;
-      d.sup_out = sup[B.order_ids[q]];
-      d.x_out = xo[B.order_ids[q]];
-      yp[q] = y[B.order_ids[q]];
       // largest-first: iteration count times (residual + transform) work
       cost[q] = (double)p.K * ((double)p.M * p.K * 0.5 + (double)p.N * G.g.logN);
     }
@@ -190,13 +207,13 @@ int wg_solve_batch(WgBatch& B, const fcmp_problem* probs, const void* const* y,
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
   HIP_TRY(hipMemcpyAsync(B.desc, desc.data(), n * sizeof(WgDesc), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(B.order, order.data(), n * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(B.yptrs, yp.data(), n * sizeof(void*), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
-  return wg_run(B, stats, st);
+  return FCMP_OK;
 }
 
 int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
   const int64_t n = B.n;
+  HIP_TRY(launch_stamp(B.t0, st));
   {
     // ---- prologue: y in entry order, kernel vector, h_0, per (class, N, M) group
     ProfScope ps(FCMP_PHASE_H0, st);
@@ -205,7 +222,7 @@ int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
       const int wk = F ? V_C128 : V_F64;
       const int pk = corr_kind(G.cls, B.opt.corr_precision);
       const int c = (int)G.count;
-      HIP_TRY(launch_gather_ptr(wk, (const void* const*)(B.yptrs + G.first), G.perm, G.y_ent,
+      HIP_TRY(launch_gather_ptr(wk, (const void* const*)(B.ptrs + G.first), G.perm, G.y_ent,
                                 G.M, G.sM, G.sM, c, st));
       HIP_TRY(launch_init_status(B.status + G.first, G.y_ent, G.M, F, G.sM, c, st));
       const size_t nlo = (size_t)1 << G.g.twS;
@@ -234,22 +251,36 @@ int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
     p.counter = B.counter;
     p.base = B.base;
     p.status = B.status;
+    p.ptrs = B.ptrs;
     p.tw64 = B.tw64;
     p.tw32 = B.tw32;
+    p.logT = WG_LOGT;
+    p.twS = WG_LOGT / 2;
     p.logNmax = B.logNmax;
-    p.twS = B.logNmax / 2;
     p.Kmax = B.Kmax;
     p.tile_bytes = B.tile_bytes;
+    p.t0 = B.t0;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int groups = (int)std::min<int64_t>(n, (int64_t)cus);
+    const int per_cu = B.per_cu > 0 ? B.per_cu : omp_wg_per_cu(p, B.opt.corr_precision);
+    const int groups = (int)std::min<int64_t>(n, (int64_t)cus * per_cu);
     HIP_TRY(launch_omp_wg(p, B.opt.corr_precision, groups, st));
   }
-  if (stats) {
+  if (stats) return wg_stats(B, stats, st);
+  return FCMP_OK;
+}
+
+int wg_stats(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
+  const int64_t n = B.n;
+  {
     std::vector<Status> hs(n);
     HIP_TRY(hipMemcpyAsync(hs.data(), B.status, n * sizeof(Status), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    int dev = 0, khz = 100000;
+    if (hipGetDevice(&dev) == hipSuccess)
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (khz <= 0) khz = 100000;
     int worst = FCMP_OK;
     for (int64_t q = 0; q < n; ++q) {
       fcmp_stats& s = stats[B.order_ids[q]];
@@ -257,7 +288,7 @@ int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
       s.status = hs[q].numeric ? FCMP_E_NUMERIC : FCMP_OK;
       const double r2 = hs[q].ynorm2 - hs[q].znorm2;
       s.res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
-      s.ms_total = 0.0;
+      s.ms_total = hs[q].t_done / (double)khz;   // completion, from the batch start
       if (hs[q].numeric) worst = FCMP_E_NUMERIC;
     }
     if (worst) return set_error(worst, "Cholesky breakdown in at least one instance");

@@ -6,6 +6,10 @@
 
 namespace fcmp {
 
+// Twiddle table size of the persistent kernel: fixed (not the batch's
+// largest N) so an instance's arithmetic never depends on its batch mates.
+constexpr int WG_LOGT = 15;
+
 struct WgGroup {
   int cls = 0, N = 0, M = 0;
   int64_t first = 0, count = 0;   // members: internal positions [first, first + count)
@@ -31,6 +35,7 @@ struct WgBatch {
   std::vector<WgGroup> groups;
   std::vector<int64_t> inst_off;   // per internal position: W, x, z region offset
   int logNmax = 1, Kmax = 1;
+  int per_cu = 0;                  // resident workgroups per CU (0: occupancy query)
   size_t tile_bytes = 0;
   char* base = nullptr;
   double2* tw64 = nullptr;
@@ -38,8 +43,9 @@ struct WgBatch {
   WgDesc* desc = nullptr;
   int32_t* order = nullptr;
   int* counter = nullptr;
+  uint64_t* t0 = nullptr;          // device clock at the batch start
   Status* status = nullptr;
-  void** yptrs = nullptr;
+  void** ptrs = nullptr;           // 3n: y, support, x (internal order)
   size_t total = 0;
 };
 
@@ -47,10 +53,18 @@ bool wg_eligible(const fcmp_problem& p, const fcmp_options& o);
 int wg_plan_init(WgBatch& B, int64_t n, const fcmp_problem* probs, const int64_t* ids,
                  const fcmp_options* opt);
 void wg_layout(WgBatch& B, const fcmp_problem* probs, char* base);
-// Builds the tables and descriptors (host work, synchronises) then runs.
+// Builds the tables and descriptors and uploads them (host work; synchronises).
+int wg_build(WgBatch& B, const fcmp_problem* probs, hipStream_t st);
+// Host array of 3n pointers (y, support, x) in the internal order.
+void wg_host_ptrs(const WgBatch& B, const void* const* y, int32_t* const* sup,
+                  void* const* xo, void** out);
+// wg_build + pointer upload + wg_run.
 int wg_solve_batch(WgBatch& B, const fcmp_problem* probs, const void* const* y,
                    int32_t* const* sup, void* const* xo, fcmp_stats* stats, hipStream_t st);
 // Device work only: prologue + persistent launch (stats synchronise).
 int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st);
+// Reads the per-instance status (synchronises): iterations, residual norm,
+// completion time from the batch start in ms_total.
+int wg_stats(WgBatch& B, fcmp_stats* stats, hipStream_t st);
 
 }  // namespace fcmp

@@ -144,7 +144,7 @@ struct Status {
   double  znorm2;      // ||z||^2 = ||y||^2 - ||r||^2
   double  ynorm2;      // ||y||^2
   double  last_key;    // |h|^2 of the last pick
-  double  pad2;
+  double  t_done;      // persistent batches: device wall-clock ticks at completion
 };
 
 }  // namespace fcmp

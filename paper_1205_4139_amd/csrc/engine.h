@@ -105,6 +105,8 @@ class ProfScope {
   hipEvent_t a_ = nullptr;
 };
 bool prof_enabled();
+// Phase events are not recorded by this thread while suspended (graph capture).
+void prof_suspend(bool on);
 int profile_enable(int enable);
 int profile_read(fcmp_profile* out, int reset);
 

@@ -185,8 +185,6 @@ struct WgDesc {
   int64_t off_h0;         // FP64[N]
   int64_t off_W;          // FP64[K(K+1)/2]
   int64_t off_x, off_z;   // FP64[K]
-  int32_t* sup_out;       // caller's support (K)
-  void* x_out;            // caller's x (K)
 };
 struct WgParams {
   const WgDesc* desc;
@@ -195,13 +193,22 @@ struct WgParams {
   int* counter;           // zeroed before the launch
   char* base;             // workspace base for the offsets
   Status* status;         // per instance (indexed like desc)
-  const double2* tw64;    // two-level twiddles for Nmax, sign +
+  void* const* ptrs;      // 3n device pointers indexed like desc: y, support, x
+  const double2* tw64;    // two-level twiddles of the fixed table size 2^logT, sign +
   const float2* tw32;
-  int logNmax, twS;
+  int logT, twS;          // table size and its lo/hi split (independent of the batch)
+  int logNmax;            // largest N in the batch (exclusion bitmap)
   int Kmax;
+  const uint64_t* t0;     // device wall-clock ticks at the batch start
   size_t tile_bytes;      // LDS bytes reserved for the transform tile
 };
 hipError_t launch_omp_wg(const WgParams& p, int precision, int groups, hipStream_t st);
+// workgroups of the persistent kernel that fit on one CU at once
+int omp_wg_per_cu(const WgParams& p, int precision);
+hipError_t launch_stamp(uint64_t* dst, hipStream_t st);
+// Raises (never lowers) a kernel's dynamic-LDS limit; safe when several host
+// threads launch the same kernel with different LDS sizes.
+hipError_t raise_lds_limit(const void* kernel, size_t bytes);
 size_t omp_wg_lds_bytes(const WgParams& p);
 hipError_t launch_noise(int fourier, const void* clean, const void* noise, double snr_db,
                         void* y, int M, hipStream_t st);

@@ -358,16 +358,12 @@ hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st) {
     const size_t lds_a = (size_t)n * wb + 16;
     const int cblocks = (n + L_THREADS - 1) / L_THREADS;
     if (p.fourier) {
-      if (lds_a > 65536)
-        hipFuncSetAttribute((const void*)ls_a_kernel<true>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_a);
+      raise_lds_limit((const void*)ls_a_kernel<true>, lds_a);
       hipLaunchKernelGGL(ls_a_kernel<true>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
       hipLaunchKernelGGL(ls_b_kernel<true>, dim3(G, ninst), dim3(L_THREADS), 0, st, p);
       hipLaunchKernelGGL(ls_c_kernel<true>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
     } else {
-      if (lds_a > 65536)
-        hipFuncSetAttribute((const void*)ls_a_kernel<false>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_a);
+      raise_lds_limit((const void*)ls_a_kernel<false>, lds_a);
       hipLaunchKernelGGL(ls_a_kernel<false>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
       hipLaunchKernelGGL(ls_b_kernel<false>, dim3(G, ninst), dim3(L_THREADS), 0, st, p);
       hipLaunchKernelGGL(ls_c_kernel<false>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
@@ -378,14 +374,10 @@ hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st) {
   const size_t wb = p.fourier ? 16 : 8;
   const size_t lds = 2 * n * wb + (size_t)n * 4 + 16;
   if (p.fourier) {
-    if (lds > 65536)
-      hipFuncSetAttribute((const void*)ls_kernel<true>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    raise_lds_limit((const void*)ls_kernel<true>, lds);
     hipLaunchKernelGGL(ls_kernel<true>, dim3(ninst), dim3(L_THREADS), lds, st, p);
   } else {
-    if (lds > 65536)
-      hipFuncSetAttribute((const void*)ls_kernel<false>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    raise_lds_limit((const void*)ls_kernel<false>, lds);
     hipLaunchKernelGGL(ls_kernel<false>, dim3(ninst), dim3(L_THREADS), lds, st, p);
   }
   return hipGetLastError();

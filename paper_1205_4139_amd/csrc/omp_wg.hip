@@ -141,7 +141,8 @@ __device__ bool wg_ls(const WgDesc& d, char* base, const WgLds& s, int t, uint32
 // One OMP solve; V is the correlation type (float/double for Hadamard,
 // float2/double2 for Fourier).
 template <class V>
-__device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Status* stat) {
+__device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Status* stat,
+                         int32_t* sup_out, void* x_out) {
   constexpr bool F = VT<V>::cplx;
   using Wd = typename VT<V>::Wide;
   const int tid = threadIdx.x;
@@ -153,7 +154,7 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
   const Wd* y = (const Wd*)(base + d.off_y);
   const Wd* x = (const Wd*)(base + d.off_x);
   const uint32_t mask = (uint32_t)N - 1u;
-  const int upshift = p.logNmax - logN;   // twiddle index scaling to the Nmax tables
+  const int upshift = p.logT - logN;   // twiddle index scaling to the fixed tables
   const double inv_sqrt_n = 1.0 / sqrt((double)N);
   for (int e = tid; e < (N + 31) / 32; e += WG_THREADS) s.excl[e] = 0u;
   __syncthreads();
@@ -246,7 +247,7 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
         }
       }
       __syncthreads();
-      lds_transform<F>(tile, N, logN, 1, 0, TwSel<V>::lo(s), TwSel<V>::hi(s), p.twS, p.logNmax, +1);
+      lds_transform<F>(tile, N, logN, 1, 0, TwSel<V>::lo(s), TwSel<V>::hi(s), p.twS, p.logT, +1);
       for (int j = tid; j < N; j += WG_THREADS) {
         if ((s.excl[j >> 5] >> (j & 31)) & 1u) continue;
         const double kk2 = vmag2(vscale(tile[lds_addr(j)], inv_sqrt_n));
@@ -263,16 +264,17 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
   }
   // results
   const Wd* xr = (const Wd*)(base + d.off_x);
-  Wd* xo = (Wd*)d.x_out;
+  Wd* xo = (Wd*)x_out;
   for (int i = tid; i < K; i += WG_THREADS) {
     const bool ok = i < iters;
-    d.sup_out[i] = ok ? s.lam[i] : -1;
+    sup_out[i] = ok ? s.lam[i] : -1;
     xo[i] = ok ? xr[i] : vzero(Wd());
   }
   if (tid == 0) {
     stat->iterations = iters;
     stat->numeric = numeric ? 1 : 0;
     stat->znorm2 = znorm2;
+    stat->t_done = (double)(wall_clock64() - *p.t0);
     stat->done = 1;
   }
   __syncthreads();
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(WG_THREADS) omp_wg_kernel(WgParams p) {
   __shared__ int cur;
   WgLds s;
   s.tile = smem_raw;
-  const int nlo = 1 << p.twS, nhi = (1 << p.logNmax) >> p.twS;
+  const int nlo = 1 << p.twS, nhi = (1 << p.logT) >> p.twS;
   unsigned char* q = smem_raw + ((p.tile_bytes + 15) & ~(size_t)15);
   s.tw64lo = (double2*)q; q += nlo * 16;
   s.tw64hi = (double2*)q; q += nhi * 16;
@@ -310,18 +312,20 @@ __global__ void __launch_bounds__(WG_THREADS) omp_wg_kernel(WgParams p) {
     if (i >= p.n) break;   // uniform: every wave reads the same slot
     const int di = p.order[i];
     const WgDesc d = p.desc[di];
+    int32_t* so = (int32_t*)p.ptrs[p.n + di];
+    void* xo = p.ptrs[2 * p.n + di];
     if (d.cls == FCMP_FOURIER) {
-      if (PREC == FCMP_FP32) wg_solve<float2>(p, d, s, p.status + di);
-      else wg_solve<double2>(p, d, s, p.status + di);
+      if (PREC == FCMP_FP32) wg_solve<float2>(p, d, s, p.status + di, so, xo);
+      else wg_solve<double2>(p, d, s, p.status + di, so, xo);
     } else {
-      if (PREC == FCMP_FP32) wg_solve<float>(p, d, s, p.status + di);
-      else wg_solve<double>(p, d, s, p.status + di);
+      if (PREC == FCMP_FP32) wg_solve<float>(p, d, s, p.status + di, so, xo);
+      else wg_solve<double>(p, d, s, p.status + di, so, xo);
     }
   }
 }
 
 size_t omp_wg_lds_bytes(const WgParams& p) {
-  const size_t nlo = (size_t)1 << p.twS, nhi = ((size_t)1 << p.logNmax) >> p.twS;
+  const size_t nlo = (size_t)1 << p.twS, nhi = ((size_t)1 << p.logT) >> p.twS;
   size_t b = (p.tile_bytes + 15) & ~(size_t)15;
   b += (nlo + nhi) * (16 + 8);
   b += (((size_t)1 << p.logNmax) + 31) / 32 * 4;
@@ -331,16 +335,34 @@ size_t omp_wg_lds_bytes(const WgParams& p) {
   return b;
 }
 
+__global__ void stamp_kernel(uint64_t* dst) {
+  if (threadIdx.x == 0) *dst = wall_clock64();
+}
+
+hipError_t launch_stamp(uint64_t* dst, hipStream_t st) {
+  hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, st, dst);
+  return hipGetLastError();
+}
+
+int omp_wg_per_cu(const WgParams& p, int precision) {
+  const size_t lds = omp_wg_lds_bytes(p);
+  const void* f = precision == FCMP_FP32 ? (const void*)omp_wg_kernel<FCMP_FP32>
+                                         : (const void*)omp_wg_kernel<FCMP_FP64>;
+  if (raise_lds_limit(f, lds) != hipSuccess) return 1;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, WG_THREADS, lds) != hipSuccess || nb < 1)
+    return 1;
+  return nb;
+}
+
 hipError_t launch_omp_wg(const WgParams& p, int precision, int groups, hipStream_t st) {
   const size_t lds = omp_wg_lds_bytes(p);
   if (precision == FCMP_FP32) {
-    hipError_t e = hipFuncSetAttribute((const void*)omp_wg_kernel<FCMP_FP32>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = raise_lds_limit((const void*)omp_wg_kernel<FCMP_FP32>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(omp_wg_kernel<FCMP_FP32>, dim3(groups), dim3(WG_THREADS), lds, st, p);
   } else {
-    hipError_t e = hipFuncSetAttribute((const void*)omp_wg_kernel<FCMP_FP64>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = raise_lds_limit((const void*)omp_wg_kernel<FCMP_FP64>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(omp_wg_kernel<FCMP_FP64>, dim3(groups), dim3(WG_THREADS), lds, st, p);
   }

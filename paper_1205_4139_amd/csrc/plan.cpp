@@ -186,30 +186,29 @@ static int upload_ptrs(fcmp_plan& P, const void* const* y, int32_t* const* sup, 
   return FCMP_OK;
 }
 
-int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_t* const* sup,
-               void* const* xo, fcmp_stats* stats, hipStream_t st) {
-  fcmp_options opt = P.opt;
-  if (o) {
-    int rc = validate_options(&P.shape, o);
-    if (rc) return rc;
-    if (o->algorithm != P.opt.algorithm || o->corr_precision != P.opt.corr_precision)
-      return set_error(FCMP_E_INVALID, "options differ from the plan's algorithm/precision");
-    opt = *o;
+int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats) {
+  int worst = FCMP_OK;
+  for (int64_t b = 0; b < n; ++b) {
+    stats[b].iterations = hs[b].iterations;
+    stats[b].status = hs[b].numeric ? FCMP_E_NUMERIC : FCMP_OK;
+    const double r2 = hs[b].ynorm2 - hs[b].znorm2;
+    stats[b].res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
+    stats[b].ms_total = ms;
+    if (stats[b].status != FCMP_OK) worst = stats[b].status;
   }
-  if (!y || !sup || !xo) return set_error(FCMP_E_INVALID, "NULL pointer array");
-  int rc = upload_ptrs(P, y, sup, xo, st);
-  if (rc) return rc;
+  if (worst != FCMP_OK) return set_error(worst, "Cholesky breakdown in at least one instance");
+  return FCMP_OK;
+}
+
+// Kernel vector (when asked), exclusion reset, y in entry order, status and
+// h_0 with the first identification: device work only.
+static int plan_enqueue_prefix(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
+  int rc = FCMP_OK;
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
   const int n = (int)P.n;
-  const int N = (int)P.shape.N, M = (int)P.shape.M, K = (int)P.shape.K;
+  const int N = (int)P.shape.N, M = (int)P.shape.M;
   const Geo& g = P.g;
   const EntDev en{P.ent_k, P.goff, M};
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (stats) {
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, st));
-  }
   if (opt.flags & FCMP_FLAG_RECOMPUTE_KERNEL) {
     if ((rc = plan_kernel_vector(P, st))) return rc;
   }
@@ -231,12 +230,19 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
     HIP_TRY(run_transform(P.wk, +1, g, tw_for(P, P.wk), en, XSrc{IN_SPARSE, P.wk, P.y_ent}, d,
                           P.tmp, nullptr, st, n, P.sN, P.sM, P.sP, P.sE, P.sG));
   }
-  if (P.opt.algorithm != FCMP_OMP) {
-    rc = plan_solve_set(P, opt, (int32_t* const*)sup, xo, stats, st);
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    return rc;
-  }
+  (void)rc;
+  return FCMP_OK;
+}
+
+int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
+  int rc = plan_enqueue_prefix(P, opt, st);
+  if (rc) return rc;
+  const bool F = P.shape.matrix_class == FCMP_FOURIER;
+  const int n = (int)P.n;
+  const int N = (int)P.shape.N, M = (int)P.shape.M, K = (int)P.shape.K;
+  const Geo& g = P.g;
+  const EntDev en{P.ent_k, P.goff, M};
+  const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
   LParams lp{};
   lp.N = N; lp.fourier = F;
   lp.partial = P.partial; lp.npart = transform_partials(P.wk, g);
@@ -315,6 +321,37 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
                                 (int32_t* const*)(P.dptrs + P.n), (void* const*)(P.dptrs + 2 * P.n),
                                 n, st));
   }
+  return FCMP_OK;
+}
+
+int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_t* const* sup,
+               void* const* xo, fcmp_stats* stats, hipStream_t st) {
+  fcmp_options opt = P.opt;
+  if (o) {
+    int rc = validate_options(&P.shape, o);
+    if (rc) return rc;
+    if (o->algorithm != P.opt.algorithm || o->corr_precision != P.opt.corr_precision)
+      return set_error(FCMP_E_INVALID, "options differ from the plan's algorithm/precision");
+    opt = *o;
+  }
+  if (!y || !sup || !xo) return set_error(FCMP_E_INVALID, "NULL pointer array");
+  int rc = upload_ptrs(P, y, sup, xo, st);
+  if (rc) return rc;
+  const int n = (int)P.n;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  if (P.opt.algorithm != FCMP_OMP) {
+    if ((rc = plan_enqueue_prefix(P, opt, st))) return rc;
+    rc = plan_solve_set(P, opt, (int32_t* const*)sup, xo, stats, st);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    return rc;
+  }
+  if ((rc = plan_enqueue(P, opt, st))) return rc;
   if (stats) {
     HIP_TRY(hipEventRecord(e1, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -324,16 +361,7 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
     hipEventDestroy(e1);
     std::vector<Status> hs((size_t)n);
     HIP_TRY(hipMemcpy(hs.data(), P.status, n * sizeof(Status), hipMemcpyDeviceToHost));
-    int worst = FCMP_OK;
-    for (int b = 0; b < n; ++b) {
-      stats[b].iterations = hs[b].iterations;
-      stats[b].status = hs[b].numeric ? FCMP_E_NUMERIC : FCMP_OK;
-      const double r2 = hs[b].ynorm2 - hs[b].znorm2;
-      stats[b].res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
-      stats[b].ms_total = ms;
-      if (stats[b].status != FCMP_OK) worst = stats[b].status;
-    }
-    if (worst != FCMP_OK) return set_error(worst, "Cholesky breakdown in at least one instance");
+    return plan_stats(n, hs.data(), ms, stats);
   }
   return FCMP_OK;
 }

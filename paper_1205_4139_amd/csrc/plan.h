@@ -67,6 +67,12 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st);
 int plan_solve(fcmp_plan& P, const fcmp_options* opt, const void* const* y,
                int32_t* const* sup, void* const* x, fcmp_stats* stats, hipStream_t st);
 int plan_kernel_vector(fcmp_plan& P, hipStream_t st);
+// OMP device work of one solve (no host synchronisation, so it can be
+// captured in a graph); the pointer array dptrs must already be uploaded.
+int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st);
+// Fills stats from host copies of the status records; FCMP_E_NUMERIC when any
+// instance broke down.
+int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats);
 // SP / CoSaMP for every instance of the plan (after h_0 is in place)
 int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, void* const* xo,
                    fcmp_stats* stats, hipStream_t st);

@@ -17,6 +17,7 @@ std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
 double g_ms[FCMP_NPHASE];
 int64_t g_n[FCMP_NPHASE];
+thread_local int t_suspend = 0;   // > 0 while this thread captures a graph
 
 hipEvent_t take_event() {
   if (!g_pool.empty()) {
@@ -35,7 +36,10 @@ bool prof_enabled() {
   return g_on;
 }
 
+void prof_suspend(bool on) { t_suspend += on ? 1 : -1; }
+
 ProfScope::ProfScope(int phase, hipStream_t st) : phase_(phase), st_(st) {
+  if (t_suspend > 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
   a_ = take_event();

@@ -2,7 +2,22 @@
 // the final reduction of identification partials and measurement noise.
 #include "kernels.h"
 
+#include <mutex>
+#include <unordered_map>
+
 namespace fcmp {
+
+hipError_t raise_lds_limit(const void* kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  static std::mutex mu;
+  static std::unordered_map<const void*, size_t> set;
+  std::lock_guard<std::mutex> lk(mu);
+  size_t& cur = set[kernel];
+  if (bytes <= cur) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) cur = bytes;
+  return e;
+}
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -98,7 +113,7 @@ __global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, i
   if (threadIdx.x == 0) {
     Status z;
     z.done = 0; z.numeric = 0; z.iterations = 0; z.cur_j = -1;
-    z.znorm2 = 0.0; z.ynorm2 = s; z.last_key = 0.0; z.pad2 = 0.0;
+    z.znorm2 = 0.0; z.ynorm2 = s; z.last_key = 0.0; z.t_done = 0.0;
     st[inst] = z;
   }
 }

@@ -192,11 +192,8 @@ size_t xform_lds_bytes(int vk, bool fft, const XParams& p) {
 template <class V, bool FFT, int ROLE>
 static hipError_t launch_r(const XParams& p, int groups, int ninst, size_t lds, hipStream_t st) {
   auto kfn = xform_kernel<V, FFT, ROLE>;
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute((const void*)kfn,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  hipError_t e = raise_lds_limit((const void*)kfn, lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kfn, dim3(groups, ninst), dim3(p.nthreads), lds, st, p);
   return hipGetLastError();
 }

@@ -100,3 +100,39 @@ def test_options_validation(fc):
     o.flags = 8
     n = ctypes.c_size_t(0)
     assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID
+
+
+def test_server_footprint_host_only(fc):
+    """Admission footprint: at least y + support + x, grows with K, and the
+    persistent-path footprint (no Cholesky factor in a lockstep plan's strided
+    layout, no transform scratch) is below the lockstep one."""
+    om = np.arange(256) * 4
+    small = fc.server_footprint("F", 1024, 256, 16, om)
+    assert small >= 256 * 16 + 16 * (4 + 16)
+    assert fc.server_footprint("F", 1024, 256, 32, om) > small
+    lock = fc.server_footprint("F", 1024, 256, 16, om, flags=fc.FLAG_NO_PERSISTENT)
+    assert lock > small
+    big = fc.server_footprint("H", 1 << 18, 1 << 16, 4096, np.arange(1 << 16) * 4)
+    assert big > 4096 * 4097 // 2 * 8   # the packed FP64 inverse factor
+    with pytest.raises(fc.FcmpError, match="K must be"):
+        fc.server_footprint("F", 1024, 256, 256, om)
+
+
+def test_batch_plan_query_host_only(fc):
+    oms = [(np.arange(256) * 4).astype(np.int32), (np.arange(512) * 2).astype(np.int32)]
+    probs = [("F", 1024, 256, 16, oms[0]), ("H", 1024, 512, 40, oms[1])]
+    arr = (fc.Problem * 2)()
+    for i, (cls, N, M, K, om) in enumerate(probs):
+        arr[i] = fc.Problem(fc.CLASS[cls], 0, N, M, K,
+                            om.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    o = fc.make_options()
+    a, b = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert fc.lib.fcmp_batch_query_workspace(2, arr, ctypes.byref(o), ctypes.byref(a)) == 0
+    assert fc.lib.fcmp_batch_plan_query_workspace(2, arr, ctypes.byref(o), ctypes.byref(b)) == 0
+    assert b.value >= a.value > 0
+
+
+def test_server_create_rejects_missing_pool(fc):
+    h = ctypes.c_void_p(0)
+    assert fc.lib.fcmp_server_create(ctypes.byref(h), None, 1 << 20, None) == -1
+    assert b"pool" in fc.lib.fcmp_last_error()

@@ -135,3 +135,41 @@ def test_persistent_and_lockstep_agree(fc):
     for k in range(len(insts)):
         assert np.array_equal(to_np(a[0][k]), to_np(b[0][k]))
         assert np.allclose(to_np(a[1][k]), to_np(b[1][k]), rtol=0, atol=1e-12 * np.abs(to_np(b[1][k])).max())
+
+
+@pytest.mark.parametrize("method", ["conventional", "adaptive"])
+def test_batch_plan_graph_replays_match_eager(fc, method):
+    """A batch plan replays one captured graph: persistent part plus two
+    lockstep plans (N = 2^16 is beyond one workgroup's LDS).  Every replay,
+    with eager work and synchronisations in between and with right-hand
+    sides changing between replays, is bit-identical to the eager one-shot
+    batch solve."""
+    import torch
+    insts, ys, _ = _uneven(12, 8600)
+    big = [instancegen.draw_instance("F", 65536, 8192, 24, "cgauss", 30.0, 8650 + i)
+           for i in range(2)]
+    big.append(instancegen.draw_instance("H", 65536, 8192, 24, "gauss", 30.0, 8660))
+    allin = list(insts) + big
+    ya = list(ys) + [oracle.problem.instance_measure(i, tier="transform") for i in big]
+    rng = np.random.default_rng(8670)
+    yb = []
+    for inst in allin:
+        x = np.zeros(inst.N, dtype=complex if inst.cls == "F" else float)
+        sup = rng.choice(inst.N, inst.K, replace=False)
+        x[sup] = rng.standard_normal(inst.K)
+        yb.append(oracle.measure(inst.cls, inst.N, inst.omega, x))
+    probs = [(i.cls, i.N, i.M, i.K, i.omega) for i in allin]
+    bp = fc.BatchPlan(probs, method=method, precision="fp32")
+    for rep, yset in enumerate([ya, yb, ya]):
+        yd = [to_dev(y) for y in yset]
+        s, x, st = bp.solve(yd, stats=True)
+        got_s = [to_np(t).copy() for t in s]
+        got_x = [to_np(t).copy() for t in x]
+        torch.cuda.synchronize()
+        ref_s, ref_x, ref_st = fc.batch_solve(probs, yd, method=method, precision="fp32")
+        torch.cuda.synchronize()
+        for k in range(len(allin)):
+            assert np.array_equal(got_s[k], to_np(ref_s[k])), (rep, k)
+            assert np.array_equal(got_x[k], to_np(ref_x[k])), (rep, k)
+            assert st[k].iterations == ref_st[k].iterations == allin[k].K
+    bp.close()

@@ -145,7 +145,8 @@ int fcmp_solve(const fcmp_problem* prob, const fcmp_options* opt,
  * one workgroup's LDS (N * element size <= 140 KiB, K <= 1024) run whole
  * solves, one workgroup per problem, in one persistent launch after a
  * lockstep prologue (kernel vector and h_0 per (class, N, M) group); the
- * others run as lockstep plans per shape.  Arrays are HOST arrays of n
+ * others run as lockstep plans, one per (class, N) for OMP (each problem
+ * keeps its own M and K) and one per (class, N, M, K) for SP/CoSaMP.  Arrays are HOST arrays of n
  * entries holding device pointers; stats (nullable) is a host array of n
  * (when given the call synchronises the stream). */
 int fcmp_batch_query_workspace(int64_t n, const fcmp_problem* probs,
@@ -183,8 +184,10 @@ int fcmp_batch_plan_destroy(fcmp_batch_plan* plan);
  * -- the rows of Phi in the order the transform kernels consume them and the
  * correlation kernel vector c, which the paper notes is independent of x and
  * "stored in advance" (definition after eq. (kernelsum)) -- plus every
- * per-solve buffer, for n problems of ONE shape (class, N, M, K) solved in
- * lockstep: each kernel launch of a solve covers all n instances.
+ * per-solve buffer, for n problems of one class and N solved in lockstep:
+ * each kernel launch of a solve covers all n instances.  OMP problems may
+ * differ in M and K (each makes its own K selections; the loop runs to the
+ * largest K); SP/CoSaMP plans need one (M, K).
  * probs: HOST array of n problems (each with its own Omega); the options fix
  * algorithm and correlation precision for the plan's lifetime.  Creation
  * uploads the tables, computes c and synchronises the stream.  Solves on one
@@ -212,7 +215,7 @@ int fcmp_plan_destroy(fcmp_plan* plan);
  * waves: all queued OMP requests the persistent one-workgroup-per-problem
  * kernel takes, with the same options, in one persistent launch (at most
  * max_wave); any other request as a lockstep plan with the queued requests
- * of its shape.  With several streams, stream 0 runs persistent waves only.
+ * of its class and N (OMP: K within a factor of two; SP/CoSaMP: same M, K).  With several streams, stream 0 runs persistent waves only.
  * Waves on different
  * streams overlap on the device.  A request's device state stays in its
  * wave's pool region from admission to completion; results are copied to

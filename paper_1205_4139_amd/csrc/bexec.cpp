@@ -3,7 +3,8 @@
 //
 // Problems are split into those the persistent one-workgroup-per-problem
 // kernel takes (OMP, transform tile within one workgroup's LDS) and the rest,
-// which run as lockstep plans, one per (class, N, M, K) shape.
+// which run as lockstep plans, one per (class, N) for OMP (per-instance M and
+// K) and one per (class, N, M, K) for SP and CoSaMP.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -27,7 +28,7 @@ size_t pad256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Split {
   std::vector<int64_t> wg;                  // caller indices of the persistent part
-  std::vector<std::vector<int64_t>> rest;   // caller indices per lockstep shape group
+  std::vector<std::vector<int64_t>> rest;   // caller indices per lockstep group
 };
 
 int partition(int64_t n, const fcmp_problem* probs, const fcmp_options* opt, Split& S) {
@@ -46,7 +47,8 @@ int partition(int64_t n, const fcmp_problem* probs, const fcmp_options* opt, Spl
       S.wg.push_back(b);
       continue;
     }
-    const auto key = std::make_tuple(p.matrix_class, p.N, p.M, p.K);
+    const bool omp = opt->algorithm == FCMP_OMP;
+    const auto key = std::make_tuple(p.matrix_class, p.N, omp ? 0 : p.M, omp ? 0 : p.K);
     auto it = idx.find(key);
     if (it == idx.end()) {
       idx[key] = S.rest.size();

@@ -150,11 +150,18 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   p.inst_ent2 = out.inst_ent2; p.inst_goff2 = out.inst_goff2;
   p.inst_yres = out.inst_yres; p.inst_rout = out.inst_rout;
   p.excl_mode = 0;
+  p.rsel_M = out.rsel_M; p.rsel_ntaps = out.rsel_ntaps; p.rsel_thr = out.rsel_thr;
+  p.goff_span = 1;
+  p.goff2_span = 1;
   if (single_ok(vk, g.N)) {
     p.L = g.N; p.logL = g.logN; p.B = 1;
     p.in_mode = in.mode; p.in_kind = in.kind; p.in = in.ptr;
     p.in_ss = 0; p.in_es = 1;
-    p.ent_k = en.ent_k; p.goff = nullptr; p.nent = en.M; p.logN1 = 0;
+    p.ent_k = en.ent_k; p.goff = en.goff; p.nent = en.M; p.logN1 = 0;
+    // the tables may be grouped for a two-pass transform of the same N in
+    // FP64: one workgroup takes every group
+    p.goff_span = g.ngroups;
+    p.goff2_span = g.same_out ? g.ngroups : g.ngroups2;
     p.inst_in = in.mode == IN_DENSE ? isn : ism;
     p.inst_ent = ism;
     p.out = out.out; p.out_kind = out.out ? out.kind : -1;
@@ -167,7 +174,6 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
     p.nthreads = pick_threads(g.N);
     p.role = 0;
     p.resid = out.resid ? 1 : 0;
-    p.goff2 = nullptr;
     p.log_out_es = 0;
     if (out.partial && out.excl) p.excl_mode = 1;
     return launch_xform(vk, fft, p, 1, ninst, st);

@@ -56,6 +56,9 @@ struct XSrc {
   int64_t inst_lam = 0, inst_x = 0;
 };
 struct XDst {
+  // plans with per-instance row counts: the transform residual skips the
+  // instances with rsel_M[inst] * rsel_ntaps <= rsel_thr
+  const int32_t* rsel_M = nullptr; int rsel_ntaps = 0; double rsel_thr = 0.0;
   void* out = nullptr; int kind = -1;
   void* out2 = nullptr; int kind2 = -1;
   Sel* partial = nullptr; const uint32_t* excl = nullptr;

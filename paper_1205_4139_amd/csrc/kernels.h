@@ -33,6 +33,8 @@ struct XParams {
   const int32_t* ent_k;    // sparse: k of each entry (entry order)
   const int32_t* goff;     // sparse: per-workgroup entry ranges; NULL: all entries
   int32_t nent;
+  int goff_span, goff2_span;   // table groups per workgroup (a single-workgroup
+                               // transform covers every group of the table)
   int logN1;               // sparse: k -> (i = k >> logN1, s = k & (N1-1))
   void* out;  int out_kind;    // -1: none
   void* out2; int out2_kind;   // -1: none
@@ -59,6 +61,9 @@ struct XParams {
   int64_t inst_ent2, inst_goff2, inst_yres, inst_rout;
   // staging of exclusion bits: 0 none, 1 contiguous outputs, 2 strided outputs
   int excl_mode;
+  // residual output in plans with per-instance row counts: only instances
+  // with rsel_M[inst] * rsel_ntaps > rsel_thr take the transform residual
+  const int32_t* rsel_M; int rsel_ntaps; double rsel_thr;
 };
 
 // vk: VKind of the transform arithmetic; fft: Fourier (else Hadamard)
@@ -83,6 +88,10 @@ struct RParams {
   const void* tw_hi;
   const Status* status;
   int64_t inst_ent, inst_y, inst_r, inst_lam, inst_x;
+  // per-instance row counts (nullable: M for all); with Mv, only instances
+  // with Mv[inst] * ntaps <= thr are handled here (the rest take the
+  // transform residual)
+  const int32_t* Mv; double thr;
 };
 hipError_t launch_residual(const RParams& p, int ninst, hipStream_t st);
 
@@ -128,6 +137,8 @@ struct LParams {
   void* wbuf; int64_t inst_wbuf;          // w = W g, K values
   void* vpart; int64_t inst_vpart;        // 16 partial rows of w^H W, K values each
   int64_t vpart_stride;
+  const int32_t* Kv;       // nullable: per-instance K; an instance whose K
+                           // selections are made is marked done at t = K + 1
 };
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st);
 int ls_split_groups(int t);   // workgroups per instance used at iteration t
@@ -141,14 +152,17 @@ hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam
                            const void* x, int K, int32_t* support_out, void* x_out,
                            hipStream_t st);
 hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st);
+// Mv / Kv (nullable): per-instance counts, at most M / K; NULL: M / K for all.
 hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier,
-                              int64_t inst_y, int ninst, hipStream_t st);
+                              int64_t inst_y, int ninst, hipStream_t st,
+                              const int32_t* Mv = nullptr);
 hipError_t launch_gather_ptr(int vk, const void* const* ptrs, const int32_t* idx, void* dst,
                              int64_t n, int64_t inst_idx, int64_t inst_dst, int ninst,
-                             hipStream_t st);
+                             hipStream_t st, const int32_t* Mv = nullptr);
 hipError_t launch_finalize_ptr(int fourier, const Status* status, const int32_t* lam,
                                const void* x, int K, int64_t inst_lam, int64_t inst_x,
-                               int32_t* const* sup, void* const* xo, int ninst, hipStream_t st);
+                               int32_t* const* sup, void* const* xo, int ninst, hipStream_t st,
+                               const int32_t* Kv = nullptr);
 // top-K by |v|^2 (ties to the lowest index), excluded entries skipped;
 // out: K ascending indices (fewer when fewer entries are eligible: then the
 // state flag st[4] is set and the tail is unspecified).

@@ -28,6 +28,11 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
   const int inst = blockIdx.x;
   Status* st = p.status + inst;
   if (st->done) return;
+  if (p.Kv && p.t > p.Kv[inst]) {   // its K selections are made
+    __syncthreads();
+    if (threadIdx.x == 0) st->done = 1;
+    return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = L_THREADS / 64;
   const int n = p.t - 1;     // previous selections
@@ -176,6 +181,10 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
   Status* st = p.status + inst;
   if (st->done) return;
+  if (p.Kv && p.t > p.Kv[inst]) {   // its K selections are made
+    if (gid == 0 && threadIdx.x == 0) st->done = 1;
+    return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int n = p.t - 1;
   Wd* g = (Wd*)smem_raw;

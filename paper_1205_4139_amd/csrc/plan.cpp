@@ -20,19 +20,31 @@ static int64_t pad64(int64_t v) { return (v + 63) & ~int64_t(63); }
 int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt) {
   if (n < 1) return set_error(FCMP_E_INVALID, "n must be >= 1");
   if (!probs) return set_error(FCMP_E_INVALID, "problems is NULL");
+  if (!opt) return set_error(FCMP_E_INVALID, "options is NULL");
+  P.uniform = true;
+  P.hM.assign(n, 0);
+  P.hK.assign(n, 0);
+  fcmp_problem big = probs[0];
   for (int64_t b = 0; b < n; ++b) {
     int rc = validate_problem(&probs[b], true);
     if (rc) return rc;
-    if (probs[b].matrix_class != probs[0].matrix_class || probs[b].N != probs[0].N ||
-        probs[b].M != probs[0].M || probs[b].K != probs[0].K)
-      return set_error(FCMP_E_INVALID, "plan problems must share class, N, M and K");
+    if ((rc = validate_options(&probs[b], opt))) return rc;
+    if (probs[b].matrix_class != probs[0].matrix_class || probs[b].N != probs[0].N)
+      return set_error(FCMP_E_INVALID, "plan problems must share class and N");
+    if (probs[b].M != probs[0].M || probs[b].K != probs[0].K) {
+      if (opt->algorithm != FCMP_OMP)
+        return set_error(FCMP_E_INVALID, "SP/CoSaMP plan problems must share M and K");
+      P.uniform = false;
+    }
+    P.hM[b] = (int32_t)probs[b].M;
+    P.hK[b] = (int32_t)probs[b].K;
+    big.M = std::max(big.M, probs[b].M);
+    big.K = std::max(big.K, probs[b].K);
   }
-  int rc = validate_options(&probs[0], opt);
-  if (rc) return rc;
   if (opt->algorithm != FCMP_OMP && probs[0].K > 2048)
     return set_error(FCMP_E_INVALID, "SP and CoSaMP support K <= 2048");
   P.n = n;
-  P.shape = probs[0];
+  P.shape = big;
   P.shape.omega = nullptr;
   P.opt = *opt;
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
@@ -72,8 +84,14 @@ void plan_layout(fcmp_plan& P, char* base) {
     P.pos1 = cv.take<int32_t>(n * P.sM);
   } else {
     P.ent2_k = P.ent_k;
-    P.goff2 = P.g.grouped ? P.goff : nullptr;
+    P.goff2 = P.goff;
     P.pos1 = nullptr;
+  }
+  if (!P.uniform) {
+    P.Mv = cv.take<int32_t>(n);
+    P.Kv = cv.take<int32_t>(n);
+  } else {
+    P.Mv = P.Kv = nullptr;
   }
   P.c64 = cv.take_bytes(n * P.sN * wb);
   P.cp = P.pk == P.wk ? P.c64 : cv.take_bytes(n * P.sN * pb);
@@ -129,7 +147,7 @@ int plan_kernel_vector(fcmp_plan& P, hipStream_t st) {
 }
 
 int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
-  const int64_t n = P.n, M = P.shape.M;
+  const int64_t n = P.n;
   std::vector<int32_t> ent((size_t)(n * P.sM), 0), perm((size_t)(n * P.sM), 0),
       goff((size_t)(n * P.sG), 0);
   std::vector<int32_t> ent2, goff2, pos1;
@@ -140,6 +158,7 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
   }
   HostTables t;
   for (int64_t b = 0; b < n; ++b) {
+    const int64_t M = probs[b].M;
     build_tables(P.g, probs[b].omega, (int)M, t);
     std::memcpy(&ent[b * P.sM], t.ent_k.data(), M * 4);
     std::memcpy(&perm[b * P.sM], t.perm.data(), M * 4);
@@ -162,6 +181,10 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(P.ent_k, ent.data(), ent.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P.perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(P.goff, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, st));
+  if (!P.uniform) {
+    HIP_TRY(hipMemcpyAsync(P.Mv, P.hM.data(), n * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(P.Kv, P.hK.data(), n * 4, hipMemcpyHostToDevice, st));
+  }
   int rc = plan_kernel_vector(P, st);
   if (rc) return rc;
   HIP_TRY(hipStreamSynchronize(st));
@@ -216,8 +239,8 @@ static int plan_enqueue_prefix(fcmp_plan& P, const fcmp_options& opt, hipStream_
     ProfScope ps(FCMP_PHASE_OTHER, st);
     HIP_TRY(launch_fill_u32(P.excl, 0u, P.n * P.sE, st));
     HIP_TRY(launch_gather_ptr(P.wk, (const void* const*)P.dptrs, P.perm, P.y_ent, M, P.sM, P.sM,
-                              n, st));
-    HIP_TRY(launch_init_status(P.status, P.y_ent, M, F, P.sM, n, st));
+                              n, st, P.Mv));
+    HIP_TRY(launch_init_status(P.status, P.y_ent, M, F, P.sM, n, st, P.Mv));
   }
   const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
   {
@@ -252,6 +275,12 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
   lp.inst_z = P.sK; lp.inst_x = P.sK; lp.inst_lam = P.sK; lp.inst_excl = P.sE;
   lp.wbuf = P.wbuf; lp.inst_wbuf = P.sK;
   lp.vpart = P.vpart; lp.inst_vpart = 16 * P.sK; lp.vpart_stride = P.sK;
+  lp.Kv = P.Kv;
+  // residual per instance: direct while M_i (t-1) <= thr, then through a
+  // forward transform of S_Lambda^T x
+  const double thr = P.resid_ratio * (double)N * (double)g.logN;
+  int64_t m_lo = P.hM[0], m_hi = P.hM[0];
+  for (int32_t m : P.hM) { m_lo = std::min<int64_t>(m_lo, m); m_hi = std::max<int64_t>(m_hi, m); }
   lp.t = 1;
   {
     ProfScope ps(FCMP_PHASE_LS, st);
@@ -273,9 +302,9 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
       fp.inst_h = 0; fp.inst_part = P.sP; fp.inst_excl = P.sE;
       HIP_TRY(launch_fastcorr(fp, n, &npart, st));
     } else {
-      const bool tresid =
-          (double)M * (double)(t - 1) > P.resid_ratio * (double)N * (double)g.logN;
-      if (tresid) {
+      const double work_lo = (double)m_lo * (double)(t - 1);
+      const double work_hi = (double)m_hi * (double)(t - 1);
+      if (work_hi > thr) {
         // residual through one FP64 forward transform of S_Lambda^T x
         ProfScope ps(FCMP_PHASE_RESID, st);
         XSrc src{IN_TAPS, P.wk, nullptr};
@@ -288,9 +317,11 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
         d.yres = P.y_ent; d.yres_kind = P.wk; d.rout = P.r; d.r_kind = P.pk;
         d.inst_ent2 = P.sM; d.inst_goff2 = P.g.same_out ? P.sG : P.sG2;
         d.inst_yres = P.sM; d.inst_rout = P.sM;
+        if (work_lo <= thr) { d.rsel_M = P.Mv; d.rsel_ntaps = t - 1; d.rsel_thr = thr; }
         HIP_TRY(run_transform(P.wk, -1, g, tw_for(P, P.wk), en, src, d, P.tmp, P.status, st, n,
                               P.sN, P.sM, 0, 0, P.sG));
-      } else {
+      }
+      if (work_lo <= thr) {
         ProfScope ps(FCMP_PHASE_RESID, st);
         RParams rp{};
         rp.N = N; rp.logN = g.logN; rp.twS = g.twS; rp.fourier = F; rp.M = M;
@@ -300,6 +331,7 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
         rp.status = P.status;
         rp.inst_ent = P.sM; rp.inst_y = P.sM; rp.inst_r = P.sM; rp.inst_lam = P.sK;
         rp.inst_x = P.sK;
+        if (work_hi > thr) { rp.Mv = P.Mv; rp.thr = thr; }
         HIP_TRY(launch_residual(rp, n, st));
       }
       ProfScope ps(FCMP_PHASE_CORR, st);
@@ -319,7 +351,7 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
     ProfScope ps(FCMP_PHASE_OTHER, st);
     HIP_TRY(launch_finalize_ptr(F, P.status, P.lam, P.x, K, P.sK, P.sK,
                                 (int32_t* const*)(P.dptrs + P.n), (void* const*)(P.dptrs + 2 * P.n),
-                                n, st));
+                                n, st, P.Kv));
   }
   return FCMP_OK;
 }

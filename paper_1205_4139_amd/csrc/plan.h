@@ -7,7 +7,11 @@
 
 struct fcmp_plan {
   int64_t n = 0;
-  fcmp_problem shape{};        // class, N, M, K (omega not kept)
+  fcmp_problem shape{};        // class, N, largest M and K (omega not kept)
+  bool uniform = true;         // every instance has the same M and K
+  std::vector<int32_t> hM, hK; // per-instance M and K
+  int32_t* Mv = nullptr;       // device copies (only when not uniform)
+  int32_t* Kv = nullptr;
   fcmp_options opt{};          // algorithm and precision fixed at creation
   fcmp::Geo g;
   int wk = 0, pk = 0;          // wide and correlation-precision value kinds

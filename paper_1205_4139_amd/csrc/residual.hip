@@ -27,6 +27,9 @@ __global__ void __launch_bounds__(R_THREADS) residual_kernel(RParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int inst = blockIdx.y;
   if (p.status && p.status[inst].done) return;
+  const int64_t Mi = p.Mv ? (int64_t)p.Mv[inst] : (int64_t)p.M;
+  if (p.Mv && (double)Mi * (double)p.ntaps > p.thr) return;   // transform residual's
+  if ((int64_t)blockIdx.x * (R_THREADS * R_EPT) >= Mi) return;
   const int tid = threadIdx.x;
   const int nlo = FOURIER ? (1 << p.twS) : 0;
   const int nhi = FOURIER ? (p.N >> p.twS) : 0;
@@ -50,7 +53,7 @@ __global__ void __launch_bounds__(R_THREADS) residual_kernel(RParams p) {
 #pragma unroll
   for (int u = 0; u < R_EPT; ++u) {
     const int64_t e = e0 + (int64_t)u * R_THREADS;
-    kk[u] = e < p.M ? (uint32_t)ek[e] : 0u;
+    kk[u] = e < Mi ? (uint32_t)ek[e] : 0u;
     acc[u] = vzero(Wd());
   }
   const uint32_t mask = (uint32_t)p.N - 1u;
@@ -85,7 +88,7 @@ __global__ void __launch_bounds__(R_THREADS) residual_kernel(RParams p) {
 #pragma unroll
   for (int u = 0; u < R_EPT; ++u) {
     const int64_t e = e0 + (int64_t)u * R_THREADS;
-    if (e < p.M) {
+    if (e < Mi) {
       Wd r = y[e];
       if constexpr (FOURIER) { r.x -= acc[u].x * sc; r.y -= acc[u].y * sc; }
       else r -= acc[u] * sc;

@@ -5,8 +5,9 @@
 // caller's pool and request slots free up, and run them as waves:
 //  * a persistent wave: every queued OMP problem the one-workgroup-per-problem
 //    kernel takes (up to max_wave, same options), solved in one launch;
-//  * a lockstep wave: requests of one shape the persistent kernel does not
-//    take (large N or K, SP, CoSaMP), solved as one lockstep plan.
+//  * a lockstep wave: requests the persistent kernel does not take (large N
+//    or K, SP, CoSaMP) that share class and N (and, for OMP, K within a
+//    factor of two; for SP and CoSaMP, M and K), solved as one lockstep plan.
 // With several streams worker 0 runs persistent waves only, so small requests
 // never queue behind large ones; the other workers take the oldest large
 // request first.  Waves on different streams overlap on the device.  Each request's device state
@@ -114,8 +115,19 @@ bool same_opts(const fcmp_options& a, const fcmp_options& b) {
          a.switch_t == b.switch_t && a.flags == b.flags;
 }
 
-bool same_shape(const fcmp_problem& a, const fcmp_problem& b) {
-  return a.matrix_class == b.matrix_class && a.N == b.N && a.M == b.M && a.K == b.K;
+int log2_ceil(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+// Requests that may share a lockstep wave: OMP plans take per-instance M and
+// K, so (class, N) and K within a factor of two (a wave ends with its
+// longest solve); SP and CoSaMP need one shape.
+bool same_group(const fcmp_problem& a, const fcmp_problem& b, int algorithm) {
+  if (a.matrix_class != b.matrix_class || a.N != b.N) return false;
+  if (algorithm == FCMP_OMP) return log2_ceil(a.K) == log2_ceil(b.K);
+  return a.M == b.M && a.K == b.K;
 }
 
 // Device bytes of the solver state of n requests run as one wave.
@@ -289,7 +301,8 @@ bool form_wave(fcmp_server* S, int worker, std::vector<Req*>& w, bool& small, si
       std::vector<Req*> cand{h};
       for (size_t j = k + 1; j < S->queue.size() && (int)cand.size() < std::min(slots, 64); ++j) {
         Req* r = S->queue[j];
-        if (!r->small && same_shape(r->prob, h->prob) && same_opts(r->opt, h->opt))
+        if (!r->small && same_opts(r->opt, h->opt) &&
+            same_group(r->prob, h->prob, h->opt.algorithm))
           cand.push_back(r);
       }
       size_t sb = 0;

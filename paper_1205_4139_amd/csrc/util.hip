@@ -103,9 +103,11 @@ hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st
 }
 
 // status[inst] = {0...}, ynorm2 = ||y||^2 (one workgroup per instance)
-__global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, int64_t inst_y) {
+__global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, int64_t inst_y,
+                                   const int32_t* Mv, int per_row) {
   __shared__ double dred[16];
   const int inst = blockIdx.x;
+  if (Mv) nreal = (int64_t)Mv[inst] * per_row;
   const double* yi = y + (int64_t)inst * inst_y;
   double s = 0.0;
   for (int64_t e = threadIdx.x; e < nreal; e += blockDim.x) s += yi[e] * yi[e];
@@ -119,11 +121,11 @@ __global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, i
 }
 
 hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier, int64_t inst_y,
-                              int ninst, hipStream_t st) {
+                              int ninst, hipStream_t st, const int32_t* Mv) {
   const int64_t nreal = fourier ? 2 * (int64_t)M : M;
   const int64_t istride = fourier ? 2 * inst_y : inst_y;
   hipLaunchKernelGGL(init_status_kernel, dim3(ninst), dim3(256), 0, st, st_dev,
-                     (const double*)y, nreal, istride);
+                     (const double*)y, nreal, istride, Mv, fourier ? 2 : 1);
   return hipGetLastError();
 }
 
@@ -153,33 +155,37 @@ hipError_t launch_noise(int fourier, const void* clean, const void* noise, doubl
 // dst[b][p] = src_b[idx[b][p]] with src_b = ptrs[b] (per-instance caller buffers)
 template <class T>
 __global__ void gather_ptr_kernel(const T* const* ptrs, const int32_t* idx, T* dst, int64_t n,
-                                  int64_t ii, int64_t id) {
+                                  int64_t ii, int64_t id, const int32_t* Mv) {
   const int inst = blockIdx.y;
   const T* src = ptrs[inst];
+  if (Mv) n = Mv[inst];
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (int64_t)gridDim.x * blockDim.x)
     dst[inst * id + e] = src[idx[inst * ii + e]];
 }
 
 hipError_t launch_gather_ptr(int vk, const void* const* ptrs, const int32_t* idx, void* dst,
-                             int64_t n, int64_t ii, int64_t id, int ninst, hipStream_t st) {
+                             int64_t n, int64_t ii, int64_t id, int ninst, hipStream_t st,
+                             const int32_t* Mv) {
   if (n <= 0) return hipSuccess;
   int64_t groups = (n + 255) / 256;
   if (groups > 1024) groups = 1024;
   dim3 grid((unsigned)groups, ninst);
   if (vbytes(vk) == 16)
     hipLaunchKernelGGL(gather_ptr_kernel<double2>, grid, dim3(256), 0, st,
-                       (const double2* const*)ptrs, idx, (double2*)dst, n, ii, id);
+                       (const double2* const*)ptrs, idx, (double2*)dst, n, ii, id, Mv);
   else
     hipLaunchKernelGGL(gather_ptr_kernel<double>, grid, dim3(256), 0, st,
-                       (const double* const*)ptrs, idx, (double*)dst, n, ii, id);
+                       (const double* const*)ptrs, idx, (double*)dst, n, ii, id, Mv);
   return hipGetLastError();
 }
 
 template <class Wd>
 __global__ void finalize_ptr_kernel(const Status* status, const int32_t* lam, const Wd* x, int K,
-                                    int64_t il, int64_t ix, int32_t* const* sup, Wd* const* xo) {
+                                    int64_t il, int64_t ix, int32_t* const* sup, Wd* const* xo,
+                                    const int32_t* Kv) {
   const int inst = blockIdx.y;
+  if (Kv) K = Kv[inst];
   const int it = status[inst].iterations;
   int32_t* s = sup[inst];
   Wd* xd = xo[inst];
@@ -192,14 +198,15 @@ __global__ void finalize_ptr_kernel(const Status* status, const int32_t* lam, co
 
 hipError_t launch_finalize_ptr(int fourier, const Status* status, const int32_t* lam,
                                const void* x, int K, int64_t il, int64_t ix,
-                               int32_t* const* sup, void* const* xo, int ninst, hipStream_t st) {
+                               int32_t* const* sup, void* const* xo, int ninst, hipStream_t st,
+                               const int32_t* Kv) {
   dim3 grid((K + 255) / 256, ninst);
   if (fourier)
     hipLaunchKernelGGL(finalize_ptr_kernel<double2>, grid, dim3(256), 0, st, status, lam,
-                       (const double2*)x, K, il, ix, sup, (double2* const*)xo);
+                       (const double2*)x, K, il, ix, sup, (double2* const*)xo, Kv);
   else
     hipLaunchKernelGGL(finalize_ptr_kernel<double>, grid, dim3(256), 0, st, status, lam,
-                       (const double*)x, K, il, ix, sup, (double* const*)xo);
+                       (const double*)x, K, il, ix, sup, (double* const*)xo, Kv);
   return hipGetLastError();
 }
 

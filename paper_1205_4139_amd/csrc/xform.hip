@@ -20,6 +20,7 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int inst = blockIdx.y;
   if (p.status && p.status[inst].done) return;
+  if (p.rsel_M && (double)p.rsel_M[inst] * (double)p.rsel_ntaps <= p.rsel_thr) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   const int g = blockIdx.x;
   const int B = p.B, L = p.L, logL = p.logL;
@@ -78,8 +79,8 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
     int lo = 0, hi = p.nent;
     if (p.goff) {
       const int32_t* go = p.goff + (int64_t)inst * p.inst_goff;
-      lo = go[g];
-      hi = go[g + 1];
+      lo = go[g * p.goff_span];
+      hi = go[(g + 1) * p.goff_span];
     }
     const int32_t* ek = p.ent_k + (int64_t)inst * p.inst_ent;
     const int mask1 = (1 << p.logN1) - 1;
@@ -104,8 +105,8 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
     int lo = 0, hi = p.nent2;
     if (p.goff2) {
       const int32_t* go = p.goff2 + (int64_t)inst * p.inst_goff2;
-      lo = go[g];
-      hi = go[g + 1];
+      lo = go[g * p.goff2_span];
+      hi = go[(g + 1) * p.goff2_span];
     }
     const int32_t* ek = p.ent2_k + (int64_t)inst * p.inst_ent2;
     const int32_t* pos1 = p.pos1 ? p.pos1 + (int64_t)inst * p.inst_ent2 : nullptr;

@@ -79,17 +79,30 @@ def test_solve_rejects_null_pointers_without_device(fc):
     assert b"NULL" in fc.lib.fcmp_last_error()
 
 
-def test_plan_requires_one_shape(fc):
+def test_plan_shape_rules(fc):
+    """OMP plans take one class and N with per-problem M and K; SP plans need
+    one (M, K); different N is always rejected."""
     probs = (fc.Problem * 2)()
     oms = [np.arange(256, dtype=np.int32) * 4, np.arange(128, dtype=np.int32) * 8]
-    for i, (M, om) in enumerate(zip((256, 128), oms)):
-        probs[i] = fc.Problem(0, 0, 1024, M, 16, om.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
-    o = fc.make_options()
+
+    def fill(N2=1024, K2=16):
+        for i, (M, om, N, K) in enumerate(zip((256, 128), oms, (1024, N2), (16, K2))):
+            probs[i] = fc.Problem(0, 0, N, M, K, om.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     n = ctypes.c_size_t(0)
+    fill(K2=20)
+    o = fc.make_options()
+    assert fc.lib.fcmp_plan_query_workspace(2, probs, ctypes.byref(o), ctypes.byref(n)) == 0
+    mixed = n.value
+    o_sp = fc.make_options("sp")
+    rc = fc.lib.fcmp_plan_query_workspace(2, probs, ctypes.byref(o_sp), ctypes.byref(n))
+    assert rc == fc.E_INVALID and b"share M and K" in fc.lib.fcmp_last_error()
+    fill(N2=2048)
     rc = fc.lib.fcmp_plan_query_workspace(2, probs, ctypes.byref(o), ctypes.byref(n))
-    assert rc == fc.E_INVALID
+    assert rc == fc.E_INVALID and b"class and N" in fc.lib.fcmp_last_error()
+    fill(K2=20)
     rc = fc.lib.fcmp_batch_query_workspace(2, probs, ctypes.byref(o), ctypes.byref(n))
     assert rc == 0 and n.value > 0
+    assert mixed > 0
 
 
 def test_options_validation(fc):

@@ -173,3 +173,29 @@ def test_batch_plan_graph_replays_match_eager(fc, method):
             assert np.array_equal(got_x[k], to_np(ref_x[k])), (rep, k)
             assert st[k].iterations == ref_st[k].iterations == allin[k].K
     bp.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lockstep_plan_with_mixed_m_and_k(fc, precision, monkeypatch):
+    """One lockstep plan over problems of one class and N with different M
+    and K: every problem stops after its own K selections and equals its
+    solve alone bit for bit; with the residual switch pulled in, instances
+    take the direct and the transform residual in the same iterations."""
+    monkeypatch.setenv("FCMP_RESID_RATIO", "0.5")
+    shapes = [(4096, 90), (1500, 80), (3000, 40), (2000, 100)]
+    insts = [instancegen.draw_instance("F", 16384, M, K, "cgauss", 30.0, 8700 + i)
+             for i, (M, K) in enumerate(shapes)]
+    ys = [oracle.problem.instance_measure(i, tier="transform") for i in insts]
+    probs = [(i.cls, i.N, i.M, i.K, i.omega) for i in insts]
+    sups, xs, stats = fc.batch_solve(probs, [to_dev(y) for y in ys], precision=precision,
+                                     flags=fc.FLAG_NO_PERSISTENT)
+    for k, (inst, y) in enumerate(zip(insts, ys)):
+        assert stats[k].iterations == inst.K
+        alone = fc.solve(inst.cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y),
+                         precision=precision)
+        assert np.array_equal(to_np(alone.support), to_np(sups[k])), k
+        assert np.array_equal(to_np(alone.x), to_np(xs[k])), k
+        ref = oracle.omp(oracle.make_operator(inst.cls, inst.N, inst.omega), y, inst.K)
+        if certify.certified(ref, precision):
+            assert list(to_np(sups[k])) == list(ref.support)
+            assert np.linalg.norm(to_np(xs[k]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)

@@ -237,6 +237,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (the reference "
+                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -251,6 +254,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 18          # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     B = args.batch
     insts, ys = make_inputs(B, dev)
     print(f"[bench] inputs ready: B={B} N={N} M={M} K={K}", file=sys.stderr, flush=True)
@@ -290,6 +300,8 @@ def main():
                                 "solves_per_s": round(B / t_step, 3)}}
     for meth in ("adaptive", "fast"):
         steps = args.fast_steps if meth == "fast" else args.steps
+        if steps <= 0:
+            continue
         t = time_steps(lambda: plan.solve(ys, method=meth), steps, 1 if meth != "fast" else 0)
         methods[meth] = {"ms_per_step": round(t * 1e3, 3), "solves_per_s": round(B / t, 3)}
         print(f"[bench] {meth}: {t*1e3:.2f} ms/step", file=sys.stderr, flush=True)

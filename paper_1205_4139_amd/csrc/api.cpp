@@ -40,7 +40,7 @@ void carve_common(Carver& cv, const Geo& g, int M, Common& c) {
   c.ent_k = cv.take<int32_t>(M);
   c.perm = cv.take<int32_t>(M);
   c.goff = cv.take<int32_t>(g.ngroups + 1);
-  const size_t ntw = ((size_t)1 << g.twS) + ((size_t)g.N >> g.twS);
+  const size_t ntw = (size_t)tw_count(g);
   c.tw64 = cv.take<double2>(ntw);
   c.tw32 = cv.take<float2>(ntw);
   c.tmp = cv.take_bytes((size_t)g.N * vbytes(wide_kind(g.fourier)));
@@ -67,8 +67,9 @@ int upload_common(const Geo& g, const fcmp_problem* prob, const Common& c, hipSt
 
 TwDev tw_for(int vk, const Geo& g, const Common& c) {
   const size_t nlo = (size_t)1 << g.twS;
-  if (vk == V_C64) return TwDev{c.tw32, c.tw32 + nlo};
-  return TwDev{c.tw64, c.tw64 + nlo};
+  const size_t nst = nlo + ((size_t)g.N >> g.twS);
+  if (vk == V_C64) return TwDev{c.tw32, c.tw32 + nlo, c.tw32 + nst};
+  return TwDev{c.tw64, c.tw64 + nlo, c.tw64 + nst};
 }
 
 }  // namespace

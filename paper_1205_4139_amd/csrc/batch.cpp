@@ -58,6 +58,7 @@ int wg_plan_init(WgBatch& B, int64_t n, const fcmp_problem* probs, const int64_t
   }
   B.logNmax = 1;
   B.Kmax = 1;
+  B.hmax = 0;
   size_t tile = 64;
   for (int64_t q = 0; q < n; ++q) {
     const fcmp_problem& p = probs[B.order_ids[q]];
@@ -65,6 +66,7 @@ int wg_plan_init(WgBatch& B, int64_t n, const fcmp_problem* probs, const int64_t
     while ((int64_t(1) << l) < p.N) ++l;
     B.logNmax = std::max(B.logNmax, l);
     B.Kmax = std::max(B.Kmax, (int)p.K);
+    if (p.matrix_class == FCMP_FOURIER && p.N / 16 >= 2) B.hmax = std::max(B.hmax, (int)(p.N / 16));
     const int ck = corr_kind(p.matrix_class, opt->corr_precision);
     tile = std::max(tile, (size_t)(p.N + (p.N >> 5) + 1) * vbytes(ck));
     tile = std::max(tile, (size_t)(2 * p.K + 2) * 16);
@@ -78,7 +80,8 @@ void wg_layout(WgBatch& B, const fcmp_problem* probs, char* base) {
   Carver cv;
   cv.base = base;
   const int twS = WG_LOGT / 2;
-  const size_t ntw = ((size_t)1 << twS) + (((size_t)1 << WG_LOGT) >> twS);
+  const size_t ntw = ((size_t)1 << twS) + (((size_t)1 << WG_LOGT) >> twS) +
+                     (size_t)stage_tw_count(B.hmax);
   B.tw64 = cv.take<double2>(ntw);
   B.tw32 = cv.take<float2>(ntw);
   B.desc = cv.take<WgDesc>(B.n);
@@ -97,9 +100,8 @@ void wg_layout(WgBatch& B, const fcmp_problem* probs, char* base) {
     G.sN = pad64(G.N);
     G.sG = pad64(G.g.ngroups + 1);
     const int64_t c = G.count;
-    const int nlo = 1 << G.g.twS, nhi = G.N >> G.g.twS;
-    G.tw64 = cv.take<double2>(nlo + nhi);
-    G.tw32 = cv.take<float2>(nlo + nhi);
+    G.tw64 = cv.take<double2>(tw_count(G.g));
+    G.tw32 = cv.take<float2>(tw_count(G.g));
     G.ent_k = cv.take<int32_t>(c * G.sM);
     G.perm = cv.take<int32_t>(c * G.sM);
     G.goff = cv.take<int32_t>(c * G.sG);
@@ -164,10 +166,17 @@ int wg_build(WgBatch& B, const fcmp_problem* probs, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(G.goff, goff.data(), goff.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipStreamSynchronize(st));
   }
-  // fixed-size twiddles for the persistent kernel
+  // fixed-size twiddles for the persistent kernel: two-level table of 2^15
+  // points, then the stage table up to span B.hmax
   {
     Geo gm = make_geo(true, 1 << WG_LOGT);
+    gm.hmax = 0;
     build_tables(gm, nullptr, 0, t);
+    std::vector<double2> s64;
+    std::vector<float2> s32;
+    build_stage_table(B.hmax, s64, s32);
+    t.tw64.insert(t.tw64.end(), s64.begin(), s64.end());
+    t.tw32.insert(t.tw32.end(), s32.begin(), s32.end());
     HIP_TRY(hipMemcpyAsync(B.tw64, t.tw64.data(), t.tw64.size() * 16, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(B.tw32, t.tw32.data(), t.tw32.size() * 8, hipMemcpyHostToDevice, st));
   }
@@ -226,7 +235,8 @@ int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
                                 G.M, G.sM, G.sM, c, st));
       HIP_TRY(launch_init_status(B.status + G.first, G.y_ent, G.M, F, G.sM, c, st));
       const size_t nlo = (size_t)1 << G.g.twS;
-      const TwDev tw{G.tw64, G.tw64 + nlo};
+      const size_t nhi = (size_t)G.N >> G.g.twS;
+      const TwDev tw{G.tw64, G.tw64 + nlo, G.tw64 + nlo + nhi};
       const EntDev en{G.ent_k, G.goff, G.M};
       XDst d;
       d.out = G.c64; d.kind = wk;
@@ -254,6 +264,11 @@ int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
     p.ptrs = B.ptrs;
     p.tw64 = B.tw64;
     p.tw32 = B.tw32;
+    {
+      const size_t nlo = (size_t)1 << (WG_LOGT / 2), nhi = ((size_t)1 << WG_LOGT) >> (WG_LOGT / 2);
+      p.tws64 = B.tw64 + nlo + nhi;
+      p.tws32 = B.tw32 + nlo + nhi;
+    }
     p.logT = WG_LOGT;
     p.twS = WG_LOGT / 2;
     p.logNmax = B.logNmax;
@@ -262,7 +277,7 @@ int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
     p.t0 = B.t0;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const int per_cu = B.per_cu > 0 ? B.per_cu : omp_wg_per_cu(p, B.opt.corr_precision);
     const int groups = (int)std::min<int64_t>(n, (int64_t)cus * per_cu);
     HIP_TRY(launch_omp_wg(p, B.opt.corr_precision, groups, st));
@@ -279,7 +294,7 @@ int wg_stats(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
     HIP_TRY(hipStreamSynchronize(st));
     int dev = 0, khz = 100000;
     if (hipGetDevice(&dev) == hipSuccess)
-      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+      (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
     if (khz <= 0) khz = 100000;
     int worst = FCMP_OK;
     for (int64_t q = 0; q < n; ++q) {

@@ -9,6 +9,9 @@ namespace fcmp {
 // Twiddle table size of the persistent kernel: fixed (not the batch's
 // largest N) so an instance's arithmetic never depends on its batch mates.
 constexpr int WG_LOGT = 15;
+// The persistent kernel's LDS transforms read the per-span stage table up to
+// span (largest Fourier N of the batch) / 16; an entry's value depends only
+// on its span, so the table's extent never changes an instance's arithmetic.
 
 struct WgGroup {
   int cls = 0, N = 0, M = 0;
@@ -35,6 +38,7 @@ struct WgBatch {
   std::vector<WgGroup> groups;
   std::vector<int64_t> inst_off;   // per internal position: W, x, z region offset
   int logNmax = 1, Kmax = 1;
+  int hmax = 0;                    // stage-table extent (Fourier instances)
   int per_cu = 0;                  // resident workgroups per CU (0: occupancy query)
   size_t tile_bytes = 0;
   char* base = nullptr;

@@ -39,7 +39,38 @@ Geo make_geo(bool fourier, int N) {
   g.ngroups = g.grouped ? (1 << g.n1) / g.B1 : 1;
   g.ngroups2 = g.grouped ? (1 << g.n2) / g.B2 : 1;
   g.same_out = !g.grouped || (fourier && g.n1 == g.n2 && g.B1 == g.B2);
+  if (fourier) {
+    // longest LDS transform of this N: the whole N when complex64 fits one
+    // workgroup, else the longer pass
+    const int maxL = single_ok(V_C64, N) ? N : (1 << std::max(g.n1, g.n2));
+    g.hmax = maxL / 16 >= 2 ? maxL / 16 : 0;
+  }
   return g;
+}
+
+int64_t tw_count(const Geo& g) {
+  return ((int64_t)1 << g.twS) + ((int64_t)g.N >> g.twS) + stage_tw_count(g.hmax);
+}
+
+void build_stage_table(int hmax, std::vector<double2>& t64, std::vector<float2>& t32) {
+  const int64_t n = stage_tw_count(hmax);
+  t64.resize(n);
+  t32.resize(n);
+  const long double two_pi = 6.283185307179586476925286766559005768L;
+  for (int64_t h = 2; h <= hmax; h *= 2) {
+    for (int64_t k = 0; k < h; ++k) {
+      for (int m = 1; m < 16; ++m) {
+        const int r = ((m & 1) << 3) | ((m & 2) << 1) | ((m & 4) >> 1) | ((m & 8) >> 3);
+        // exact reduction of the phase r k / (16 h) before the long double angle
+        const int64_t q = ((int64_t)r * k) % (16 * h);
+        const long double a = two_pi * (long double)q / (long double)(16 * h);
+        const long double c = cosl(a), s = sinl(a);
+        const int64_t e = stage_tw_offset(h) + 15 * k + m - 1;
+        t64[e] = make_double2((double)c, (double)s);
+        t32[e] = make_float2((float)c, (float)s);
+      }
+    }
+  }
 }
 
 int transform_partials(int vk, const Geo& g) {
@@ -107,6 +138,13 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
     t.tw64[q] = make_double2((double)c, (double)s);
     t.tw32[q] = make_float2((float)c, (float)s);
   }
+  if (g.hmax >= 2) {
+    std::vector<double2> s64;
+    std::vector<float2> s32;
+    build_stage_table(g.hmax, s64, s32);
+    t.tw64.insert(t.tw64.end(), s64.begin(), s64.end());
+    t.tw32.insert(t.tw32.end(), s32.begin(), s32.end());
+  }
 }
 
 const Tune& tune() {
@@ -138,6 +176,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   p.sign = sign;
   p.tw_lo = tw.lo;
   p.tw_hi = tw.hi;
+  p.tws = tw.st;
   p.status = status;
   p.excl = out.excl;
   p.inst_excl = isx;

@@ -25,7 +25,13 @@ struct Geo {
   int ngroups = 1;           // pass-1 workgroups = N1 / B1
   int ngroups2 = 1;          // pass-2 workgroups = N2 / B2
   bool same_out = true;      // pass-2 output groups coincide with pass-1 input groups
+  int hmax = 0;              // largest span of a twiddled radix-16 stage (Fourier)
 };
+// Twiddle entries per precision: two-level table (lo 2^twS, hi N >> twS) for
+// the inter-pass twiddle, then the per-span stage table of the LDS core.
+int64_t tw_count(const Geo& g);
+// Per-span stage table for spans 2..hmax (see lds_fft), sign +.
+void build_stage_table(int hmax, std::vector<double2>& t64, std::vector<float2>& t32);
 
 // Launch-shape knobs (FCMP_TILE: values per workgroup tile in the two-pass
 // transforms; FCMP_THREADS: threads per transform workgroup).
@@ -42,12 +48,12 @@ int transform_partials(int vk, const Geo& g);   // partials written by a transfo
 struct HostTables {
   std::vector<int32_t> ent_k, perm, goff;   // entry order (grouped or Omega order)
   std::vector<int32_t> ent2_k, goff2, pos1; // rows grouped by pass-2 output workgroup
-  std::vector<double2> tw64;                // lo (2^twS) then hi (N >> twS), sign +
+  std::vector<double2> tw64;                // lo (2^twS), hi (N >> twS), stage table; sign +
   std::vector<float2> tw32;
 };
 void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t);
 
-struct TwDev { const void* lo; const void* hi; };
+struct TwDev { const void* lo; const void* hi; const void* st; };
 struct EntDev { const int32_t* ent_k; const int32_t* goff; int M; };
 struct XSrc {
   int mode; int kind; const void* ptr;

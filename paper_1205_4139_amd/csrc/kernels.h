@@ -22,6 +22,14 @@ inline int vnarrow_kind(int vk) { return vcomplex(vk) ? V_C64 : V_F32; }
 // the output loop.
 enum InMode { IN_DENSE = 0, IN_SPARSE = 1, IN_SPARSE_ONES = 2, IN_TAPS = 3 };
 
+// Offset of the stage twiddles of span h (a power of two >= 2) in the
+// per-span table: span h holds, for k < h and register m = 1..15, the value
+// W_{16h}^{rev4(m) k} = e^{2 pi i rev4(m) k / (16 h)} at 15 (h - 2) + 15 k + m - 1.
+__host__ __device__ constexpr int64_t stage_tw_offset(int64_t h) { return 15 * (h - 2); }
+__host__ __device__ constexpr int64_t stage_tw_count(int64_t hmax) {
+  return hmax >= 2 ? 15 * (2 * hmax - 2) : 0;
+}
+
 struct XParams {
   int L, logL, B;          // transform length and sequences per workgroup
   int N, logN, twS;        // problem size; twiddle table split
@@ -44,7 +52,8 @@ struct XParams {
   Sel* partial;            // nullable: one (key, idx) per workgroup
   const uint32_t* excl;    // nullable exclusion bitmap (global h index)
   const void* tw_lo;       // twiddles in the transform precision, sign +
-  const void* tw_hi;
+  const void* tw_hi;       //   (two-level table, for the inter-pass twiddle)
+  const void* tws;         // per-span stage twiddles (lds_fft), sign +
   const Status* status;    // nullable: skip when status[inst].done
   // per-instance strides (blockIdx.y), in elements of each array
   int64_t inst_in, inst_ent, inst_goff, inst_out, inst_out2, inst_part, inst_excl;
@@ -211,6 +220,8 @@ struct WgParams {
   const double2* tw64;    // two-level twiddles of the fixed table size 2^logT, sign +
   const float2* tw32;
   int logT, twS;          // table size and its lo/hi split (independent of the batch)
+  const double2* tws64;   // per-span stage twiddles of the LDS transforms
+  const float2* tws32;
   int logNmax;            // largest N in the batch (exclusion bitmap)
   int Kmax;
   const uint64_t* t0;     // device wall-clock ticks at the batch start

@@ -89,43 +89,50 @@ FCMP_CTW(3, 6, -0.70710678118654752440, 0.70710678118654752440)
 FCMP_CTW(3, 7, -0.92387953251128675613, 0.38268343236508977173)
 #undef FCMP_CTW
 
-// b * e^{sign 2 pi i J / 2^(S+1)}
-template <int S, int J, class V>
-__device__ __forceinline__ V twc(V b, int sign) {
+// b * e^{+2 pi i J / 2^(s+1)} with the constant folded: the transform core
+// always runs with the + sign (callers conjugate input and output for the -
+// sign, since conj(F(conj x)) is the transform with the opposite sign).
+template <int s, int J, class V>
+__device__ __forceinline__ V twp(V b) {
   using T = decltype(b.x);
+  constexpr double c = CTw<s, J>::c, sn = CTw<s, J>::s;
+  V r;
   if constexpr (J == 0) {
-    return b;
-  } else if constexpr (CTw<S, J>::c == 0.0) {   // +-i
-    return mul_i(b, sign);
+    r = b;
+  } else if constexpr (c == 0.0) {          // i b
+    r.x = -b.y; r.y = b.x;
+  } else if constexpr (c == sn) {           // (1 + i) b / sqrt(2)
+    r.x = (T)c * (b.x - b.y); r.y = (T)c * (b.x + b.y);
+  } else if constexpr (c == -sn) {          // (-1 + i) b / sqrt(2)
+    r.x = -(T)sn * (b.x + b.y); r.y = (T)sn * (b.x - b.y);
   } else {
-    V w;
-    w.x = (T)CTw<S, J>::c;
-    w.y = sign > 0 ? (T)CTw<S, J>::s : -(T)CTw<S, J>::s;
-    return cmul(b, w);
+    r.x = (T)c * b.x - (T)sn * b.y;
+    r.y = (T)c * b.y + (T)sn * b.x;
   }
+  return r;
 }
 
-// Radix-2 DIT sub-stage s over the R = 2^S registers of one block: pairs
-// (m, m + 2^s) with twiddle b[s] * w_{2^(s+1)}^(m mod 2^s).
+// Radix-2 DIT level s over the R = 2^S registers of one block (held in
+// bit-reversed sub-block order): pairs (m, m + 2^s) with the constant twiddle
+// e^{2 pi i (m mod 2^s) / 2^(s+1)}.
 template <int S, int s, int M, class V>
-__device__ __forceinline__ void dit_pairs(V* x, const V* b, int sign) {
+__device__ __forceinline__ void dit_cpairs(V* x) {
   if constexpr (M < (1 << S)) {
     constexpr int half = 1 << s;
     if constexpr ((M & half) == 0) {
-      const V w = twc<s, (M & (half - 1))>(b[s], sign);
-      const V t = cmul(w, x[M + half]);
+      const V t = twp<s, (M & (half - 1))>(x[M + half]);
       x[M + half] = vsub(x[M], t);
       x[M] = vadd(x[M], t);
     }
-    dit_pairs<S, s, M + 1>(x, b, sign);
+    dit_cpairs<S, s, M + 1>(x);
   }
 }
 
 template <int S, int s, class V>
-__device__ __forceinline__ void dit_block(V* x, const V* b, int sign) {
+__device__ __forceinline__ void dit_const(V* x) {
   if constexpr (s < S) {
-    dit_pairs<S, s, 0>(x, b, sign);
-    dit_block<S, s + 1>(x, b, sign);
+    dit_cpairs<S, s, 0>(x);
+    dit_const<S, s + 1>(x);
   }
 }
 
@@ -150,56 +157,78 @@ __device__ __forceinline__ void wht_block(V* x) {
   }
 }
 
-// One radix-2^S stage over the LDS tile: each group holds the 2^S elements
-// base + k + m h (m < 2^S) of one sequence in registers and applies S
-// consecutive radix-2 levels (spans h .. 2^(S-1) h) to them.  The Fourier
-// form is the in-place decimation-in-time DFT on bit-reversed input, the
-// Hadamard form the in-place natural-order WHT.  Element (i, c) of the tile
-// lives at lds_addr(i*B + c).
+__device__ __forceinline__ float vconj(float v) { return v; }
+__device__ __forceinline__ double vconj(double v) { return v; }
+__device__ __forceinline__ float2 vconj(float2 v) { return make_float2(v.x, -v.y); }
+__device__ __forceinline__ double2 vconj(double2 v) { return make_double2(v.x, -v.y); }
+
+// One in-place stage over the LDS tile: each group holds the 2^S elements
+// base + k + m h (m < 2^S) of one sequence.  Fourier: the sub-blocks hold
+// decimated sub-transforms in bit-reversed order; register m is multiplied
+// by W_{2^S h}^{rev(m) k} (table, radix-16 stages only; the radix-2^r stage
+// runs first at span 1 where every twiddle is 1) and then combined by a
+// constant-twiddle DIT network (in-place decimation-in-time DFT on
+// bit-reversed input).  Hadamard: the natural-order WHT butterflies.
+// Element (i, c) of the tile lives at lds_addr(i*B + c).
 template <int S, bool FFT, class V>
-__device__ __forceinline__ void lds_stage(V* t, int L, int B, int logB, int logh, const V* lo,
-                                          const V* hi, int twS, int logN, int sign) {
+__device__ __forceinline__ void fft_stage(V* t, int L, int B, int logB, int logh, const V* tws) {
   constexpr int R = 1 << S;
   const int h = 1 << logh;
   const int ngrp = (B * L) >> S;
+  const int hb = h * B;
+  const bool affine = (hb & 31) == 0;   // padded addresses step by hb + hb/32
+  const int hs = hb + (hb >> 5);
   for (int grp = threadIdx.x; grp < ngrp; grp += blockDim.x) {
     const int c = grp & (B - 1);
     const int q = grp >> logB;
     const int k = q & (h - 1);
     const int base = ((q >> logh) << (logh + S)) + k;
+    const int e0 = base * B + c;
+    int a[R];
+    if (affine) {
+      const int a0 = lds_addr(e0);
+#pragma unroll
+      for (int m = 0; m < R; ++m) a[m] = a0 + m * hs;
+    } else {
+#pragma unroll
+      for (int m = 0; m < R; ++m) a[m] = lds_addr(e0 + m * hb);
+    }
     V x[R];
 #pragma unroll
-    for (int m = 0; m < R; ++m) x[m] = t[lds_addr((base + m * h) * B + c)];
+    for (int m = 0; m < R; ++m) x[m] = t[a[m]];
     if constexpr (FFT) {
-      V b[S];
+      if constexpr (S == 4) {
+        if (logh > 0) {
+          const V* tk = tws + stage_tw_offset(h) + 15 * k - 1;
 #pragma unroll
-      for (int s = 0; s < S; ++s)
-        b[s] = tw_lookup(lo, hi, (uint32_t)k << (logN - logh - s - 1), twS, sign);  // w_{2^(s+1) h}^k
-      dit_block<S, 0>(x, b, sign);
+          for (int m = 1; m < R; ++m) x[m] = cmul(x[m], tk[m]);
+        }
+      }
+      dit_const<S, 0>(x);
     } else {
       wht_block<S, 0>(x);
     }
 #pragma unroll
-    for (int m = 0; m < R; ++m) t[lds_addr((base + m * h) * B + c)] = x[m];
+    for (int m = 0; m < R; ++m) t[a[m]] = x[m];
   }
   __syncthreads();
 }
 
-// B interleaved length-L transforms in LDS: radix-8 stages from the
-// smallest span up, then one radix-2/4 stage for the remaining levels (radix
-// 8 keeps the block in about 60 VGPRs, so four waves per SIMD stay resident).
+// B interleaved length-L transforms in LDS with the + sign: Fourier input
+// placed in bit-reversed order (position bitrev(i) of each sequence), output
+// in natural order; Hadamard natural in and out.  A radix-2^(logL mod 4)
+// stage at span 1, then radix-16 stages; tws is the per-span twiddle table
+// (spans up to L/16; unused for Hadamard).  Ends with a barrier.
 template <bool FFT, class V>
-__device__ void lds_transform(V* t, int L, int logL, int B, int logB, const V* lo, const V* hi,
-                              int twS, int logN, int sign) {
-  int logh = 0;
-  for (; logh + 3 <= logL; logh += 3)
-    lds_stage<3, FFT>(t, L, B, logB, logh, lo, hi, twS, logN, sign);
-  switch (logL - logh) {
-    case 2: lds_stage<2, FFT>(t, L, B, logB, logh, lo, hi, twS, logN, sign); break;
-    case 1: lds_stage<1, FFT>(t, L, B, logB, logh, lo, hi, twS, logN, sign); break;
+__device__ __forceinline__ void lds_fft(V* t, int L, int logL, int B, int logB, const V* tws) {
+  int logh = logL & 3;
+  switch (logh) {
+    case 1: fft_stage<1, FFT>(t, L, B, logB, 0, tws); break;
+    case 2: fft_stage<2, FFT>(t, L, B, logB, 0, tws); break;
+    case 3: fft_stage<3, FFT>(t, L, B, logB, 0, tws); break;
     default: break;
   }
+  for (; logh < logL; logh += 4) fft_stage<4, FFT>(t, L, B, logB, logh, tws);
 }
-
 
 }  // namespace fcmp

@@ -18,6 +18,84 @@ namespace fcmp {
 
 constexpr int L_THREADS = 256;
 constexpr int L_KPT = 16;     // columns per thread in the w^H W product: K <= 4096
+constexpr int L_RB = 4;       // rows per wave in w = W g (independent loads in flight)
+constexpr int L_VB = 8;       // rows per step in w^H W (independent loads in flight)
+
+// w_i = sum_{k <= i} W(i,k) g_k for the rows i = i0 .. i0+L_RB-1 (< n) of one
+// wave: lane-strided partial sums over k, then a butterfly sum per row.  The
+// order of additions within a row does not depend on how rows are grouped.
+template <bool FOURIER, class Wd>
+__device__ __forceinline__ void ls_rows_wg(const Wd* W, const Wd* g, int i0, int n, int lane,
+                                           Wd* wout) {
+  Wd s[L_RB];
+#pragma unroll
+  for (int u = 0; u < L_RB; ++u) s[u] = vzero(Wd());
+  const int imax = min(i0 + L_RB, n) - 1;
+  for (int k = lane; k <= imax; k += 64) {
+    const Wd gk = g[k];
+#pragma unroll
+    for (int u = 0; u < L_RB; ++u) {
+      const int i = i0 + u;
+      if (i <= imax && k <= i) {
+        const Wd a = W[(int64_t)i * (i + 1) / 2 + k];
+        if constexpr (FOURIER) { const double2 t = cmul(a, gk); s[u].x += t.x; s[u].y += t.y; }
+        else s[u] += a * gk;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < L_RB; ++u) {
+    if constexpr (FOURIER) { s[u].x = wave_sum(s[u].x); s[u].y = wave_sum(s[u].y); }
+    else s[u] = wave_sum(s[u]);
+    if (lane == 0 && i0 + u < n) wout[i0 + u] = s[u];
+  }
+}
+
+// acc[q] += sum over rows i = i_first, i_first + step, ... (< n) of
+// conj(w_i) W(i, k) for k = tid + q L_THREADS <= i, rows in increasing order,
+// L_VB rows per step with their loads issued together.
+template <bool FOURIER, class Wd>
+__device__ __forceinline__ void ls_rows_wh(const Wd* W, const Wd* w, int i_first, int step, int n,
+                                           int nq, int tid, Wd* acc) {
+  int i = i_first;
+  for (; i + (L_VB - 1) * step < n; i += L_VB * step) {
+    Wd wv[L_VB];
+#pragma unroll
+    for (int u = 0; u < L_VB; ++u) wv[u] = w[i + u * step];
+#pragma unroll
+    for (int q = 0; q < L_KPT; ++q) {
+      const int k = tid + q * L_THREADS;
+      if (q < nq) {
+        Wd a[L_VB];
+#pragma unroll
+        for (int u = 0; u < L_VB; ++u) {
+          const int r = i + u * step;
+          a[u] = k <= r ? W[(int64_t)r * (r + 1) / 2 + k] : vzero(Wd());
+        }
+#pragma unroll
+        for (int u = 0; u < L_VB; ++u) {
+          const int r = i + u * step;
+          if (k <= r) {
+            if constexpr (FOURIER) { const double2 t = cmulc(wv[u], a[u]); acc[q].x += t.x; acc[q].y += t.y; }
+            else acc[q] += wv[u] * a[u];
+          }
+        }
+      }
+    }
+  }
+  for (; i < n; i += step) {
+    const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
+    const Wd wi = w[i];
+#pragma unroll
+    for (int q = 0; q < L_KPT; ++q) {
+      const int k = tid + q * L_THREADS;
+      if (q < nq && k <= i) {
+        if constexpr (FOURIER) { const double2 t = cmulc(wi, Wi[k]); acc[q].x += t.x; acc[q].y += t.y; }
+        else acc[q] += wi * Wi[k];
+      }
+    }
+  }
+}
 
 template <bool FOURIER>
 __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
@@ -70,17 +148,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
   __syncthreads();
 
   // ---- w = W g (row i of W has i+1 entries starting at i(i+1)/2)
-  for (int i = wave; i < n; i += nwaves) {
-    const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
-    Wd s = vzero(Wd());
-    for (int k = lane; k <= i; k += 64) {
-      if constexpr (FOURIER) { const double2 t = cmul(Wi[k], g[k]); s.x += t.x; s.y += t.y; }
-      else s += Wi[k] * g[k];
-    }
-    if constexpr (FOURIER) { s.x = wave_sum(s.x); s.y = wave_sum(s.y); }
-    else s = wave_sum(s);
-    if (lane == 0) w[i] = s;
-  }
+  for (int i0 = wave * L_RB; i0 < n; i0 += nwaves * L_RB) ls_rows_wg<FOURIER>(W, g, i0, n, lane, w);
   __syncthreads();
 
   // ---- d^2 = c(0) - ||w||^2, and w^H z
@@ -108,18 +176,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
 #pragma unroll
   for (int q = 0; q < L_KPT; ++q) acc[q] = vzero(Wd());
   const int nq = (n + L_THREADS - 1) / L_THREADS;
-  for (int i = 0; i < n; ++i) {
-    const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
-    const Wd wi = w[i];
-#pragma unroll
-    for (int q = 0; q < L_KPT; ++q) {
-      const int k = tid + q * L_THREADS;
-      if (q < nq && k <= i) {
-        if constexpr (FOURIER) { const double2 t = cmulc(wi, Wi[k]); acc[q].x += t.x; acc[q].y += t.y; }
-        else acc[q] += wi * Wi[k];
-      }
-    }
-  }
+  ls_rows_wh<FOURIER>(W, w, 0, 1, n, nq, tid, acc);
   __syncthreads();   // everyone is done reading g
   Wd* Wn = W + (int64_t)n * (n + 1) / 2;
 #pragma unroll
@@ -212,17 +269,9 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   Wd* wout = (Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
   for (int i = tid; i < n; i += L_THREADS) g[i] = c64[perm_index(FOURIER, (uint32_t)lam[i], j, mask)];
   __syncthreads();
-  for (int i = gid * (L_THREADS / 64) + wave; i < n; i += G * (L_THREADS / 64)) {
-    const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
-    Wd s = vzero(Wd());
-    for (int k = lane; k <= i; k += 64) {
-      if constexpr (FOURIER) { const double2 t = cmul(Wi[k], g[k]); s.x += t.x; s.y += t.y; }
-      else s += Wi[k] * g[k];
-    }
-    if constexpr (FOURIER) { s.x = wave_sum(s.x); s.y = wave_sum(s.y); }
-    else s = wave_sum(s);
-    if (lane == 0) wout[i] = s;
-  }
+  const int nw = G * (L_THREADS / 64);
+  for (int i0 = (gid * (L_THREADS / 64) + wave) * L_RB; i0 < n; i0 += nw * L_RB)
+    ls_rows_wg<FOURIER>(W, g, i0, n, lane, wout);
 }
 
 template <bool FOURIER>
@@ -272,18 +321,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
 #pragma unroll
   for (int q = 0; q < L_KPT; ++q) acc[q] = vzero(Wd());
   const int nq = (n + L_THREADS - 1) / L_THREADS;
-  for (int i = gid; i < n; i += G) {
-    const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
-    const Wd wi = w[i];
-#pragma unroll
-    for (int q = 0; q < L_KPT; ++q) {
-      const int k = tid + q * L_THREADS;
-      if (q < nq && k <= i) {
-        if constexpr (FOURIER) { const double2 t = cmulc(wi, Wi[k]); acc[q].x += t.x; acc[q].y += t.y; }
-        else acc[q] += wi * Wi[k];
-      }
-    }
-  }
+  ls_rows_wh<FOURIER>(W, w, gid, G, n, nq, tid, acc);
   Wd* vp = (Wd*)p.vpart + (int64_t)inst * p.inst_vpart + (int64_t)gid * p.vpart_stride;
 #pragma unroll
   for (int q = 0; q < L_KPT; ++q) {

@@ -15,8 +15,7 @@ constexpr int WG_THREADS = 512;
 
 struct WgLds {
   unsigned char* tile;   // transform tile (also g, w of the least squares)
-  double2* tw64lo; double2* tw64hi;
-  float2* tw32lo; float2* tw32hi;
+  double2* tw64lo; double2* tw64hi;   // two-level FP64 table (residual phases)
   uint32_t* excl;        // N bits
   int32_t* lam;          // support in selection order
   Sel* red;
@@ -26,24 +25,12 @@ struct WgLds {
 template <class T> __device__ __forceinline__ T wsh(T v, int src);
 template <> __device__ __forceinline__ double wsh<double>(double v, int src) { return __shfl(v, src, 64); }
 
-// LDS twiddle tables for the corr type
-template <class V> struct TwSel;
-template <> struct TwSel<float2> {
-  static __device__ const float2* lo(const WgLds& s) { return s.tw32lo; }
-  static __device__ const float2* hi(const WgLds& s) { return s.tw32hi; }
-};
-template <> struct TwSel<double2> {
-  static __device__ const double2* lo(const WgLds& s) { return s.tw64lo; }
-  static __device__ const double2* hi(const WgLds& s) { return s.tw64hi; }
-};
-template <> struct TwSel<float> {
-  static __device__ const float* lo(const WgLds&) { return nullptr; }
-  static __device__ const float* hi(const WgLds&) { return nullptr; }
-};
-template <> struct TwSel<double> {
-  static __device__ const double* lo(const WgLds&) { return nullptr; }
-  static __device__ const double* hi(const WgLds&) { return nullptr; }
-};
+// per-span stage twiddles (global) for the corr type
+template <class V> __device__ __forceinline__ const V* stage_tw(const WgParams& p);
+template <> __device__ __forceinline__ const float2* stage_tw<float2>(const WgParams& p) { return p.tws32; }
+template <> __device__ __forceinline__ const double2* stage_tw<double2>(const WgParams& p) { return p.tws64; }
+template <> __device__ __forceinline__ const float* stage_tw<float>(const WgParams&) { return nullptr; }
+template <> __device__ __forceinline__ const double* stage_tw<double>(const WgParams&) { return nullptr; }
 
 // Identification + least-squares update for selection number t (1-based);
 // returns false on a Cholesky breakdown.  g and w live in the tile region.
@@ -247,7 +234,7 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
         }
       }
       __syncthreads();
-      lds_transform<F>(tile, N, logN, 1, 0, TwSel<V>::lo(s), TwSel<V>::hi(s), p.twS, p.logT, +1);
+      lds_fft<F>(tile, N, logN, 1, 0, stage_tw<V>(p));
       for (int j = tid; j < N; j += WG_THREADS) {
         if ((s.excl[j >> 5] >> (j & 31)) & 1u) continue;
         const double kk2 = vmag2(vscale(tile[lds_addr(j)], inv_sqrt_n));
@@ -290,8 +277,6 @@ __global__ void __launch_bounds__(WG_THREADS) omp_wg_kernel(WgParams p) {
   unsigned char* q = smem_raw + ((p.tile_bytes + 15) & ~(size_t)15);
   s.tw64lo = (double2*)q; q += nlo * 16;
   s.tw64hi = (double2*)q; q += nhi * 16;
-  s.tw32lo = (float2*)q; q += nlo * 8;
-  s.tw32hi = (float2*)q; q += nhi * 8;
   s.excl = (uint32_t*)q; q += (((1 << p.logNmax) + 31) / 32) * 4;
   s.lam = (int32_t*)q; q += ((p.Kmax + 3) & ~3) * 4;
   q = (unsigned char*)(((uintptr_t)q + 15) & ~(uintptr_t)15);
@@ -299,9 +284,8 @@ __global__ void __launch_bounds__(WG_THREADS) omp_wg_kernel(WgParams p) {
   s.dred = (double*)q;
   for (int e = threadIdx.x; e < nlo + nhi; e += WG_THREADS) {
     const double2 a = p.tw64[e];
-    const float2 b = p.tw32[e];
-    if (e < nlo) { s.tw64lo[e] = a; s.tw32lo[e] = b; }
-    else { s.tw64hi[e - nlo] = a; s.tw32hi[e - nlo] = b; }
+    if (e < nlo) s.tw64lo[e] = a;
+    else s.tw64hi[e - nlo] = a;
   }
   __syncthreads();
   for (;;) {
@@ -327,7 +311,7 @@ __global__ void __launch_bounds__(WG_THREADS) omp_wg_kernel(WgParams p) {
 size_t omp_wg_lds_bytes(const WgParams& p) {
   const size_t nlo = (size_t)1 << p.twS, nhi = ((size_t)1 << p.logT) >> p.twS;
   size_t b = (p.tile_bytes + 15) & ~(size_t)15;
-  b += (nlo + nhi) * (16 + 8);
+  b += (nlo + nhi) * 16;
   b += (((size_t)1 << p.logNmax) + 31) / 32 * 4;
   b += (size_t)((p.Kmax + 3) & ~3) * 4;
   b = (b + 15) & ~(size_t)15;

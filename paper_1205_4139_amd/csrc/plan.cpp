@@ -71,7 +71,7 @@ void plan_layout(fcmp_plan& P, char* base) {
   Carver cv;
   cv.base = base;
   const int64_t n = P.n;
-  const size_t ntw = ((size_t)1 << P.g.twS) + ((size_t)P.g.N >> P.g.twS);
+  const size_t ntw = (size_t)tw_count(P.g);
   const size_t wb = vbytes(P.wk), pb = vbytes(P.pk);
   P.tw64 = cv.take<double2>(ntw);
   P.tw32 = cv.take<float2>(ntw);
@@ -130,8 +130,9 @@ void plan_layout(fcmp_plan& P, char* base) {
 
 static TwDev tw_for(const fcmp_plan& P, int vk) {
   const size_t nlo = (size_t)1 << P.g.twS;
-  if (vk == V_C64) return TwDev{P.tw32, P.tw32 + nlo};
-  return TwDev{P.tw64, P.tw64 + nlo};
+  const size_t nst = nlo + ((size_t)P.g.N >> P.g.twS);
+  if (vk == V_C64) return TwDev{P.tw32, P.tw32 + nlo, P.tw32 + nst};
+  return TwDev{P.tw64, P.tw64 + nlo, P.tw64 + nst};
 }
 
 int plan_kernel_vector(fcmp_plan& P, hipStream_t st) {

@@ -59,8 +59,9 @@ Inst inst_view(const fcmp_plan& P, int64_t b) {
 
 TwDev tw_of(const fcmp_plan& P, int vk) {
   const size_t nlo = (size_t)1 << P.g.twS;
-  if (vk == V_C64) return TwDev{P.tw32, P.tw32 + nlo};
-  return TwDev{P.tw64, P.tw64 + nlo};
+  const size_t nst = nlo + ((size_t)P.g.N >> P.g.twS);
+  if (vk == V_C64) return TwDev{P.tw32, P.tw32 + nlo, P.tw32 + nst};
+  return TwDev{P.tw64, P.tw64 + nlo, P.tw64 + nst};
 }
 
 // h = Phi^H (y - Phi_S a) into P.hbuf; returns the value kind of h.

@@ -30,12 +30,14 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   const int tile_alloc = tile_n + (tile_n >> 5) + 1;
   V* tile = (V*)smem_raw;
   V* twlo = tile + tile_alloc;
-  const int nlo = FFT ? (1 << p.twS) : 0;
-  const int nhi = FFT ? (p.N >> p.twS) : 0;
+  const bool itw = FFT && p.inter_tw;
+  const int nlo = itw ? (1 << p.twS) : 0;
+  const int nhi = itw ? (p.N >> p.twS) : 0;
   V* twhi = twlo + nlo;
   Sel* red = (Sel*)(((uintptr_t)(twhi + nhi) + 15) & ~(uintptr_t)15);
+  const bool neg = p.sign < 0;   // conj(F(conj x)): the core runs with the + sign
 
-  if constexpr (FFT) {
+  if (itw) {
     const V* glo = (const V*)p.tw_lo;
     const V* ghi = (const V*)p.tw_hi;
     for (int e = tid; e < nlo; e += nt) twlo[e] = glo[e];
@@ -49,8 +51,9 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
       int c, i;
       if (p.in_es == 1) { c = e >> logL; i = e & (L - 1); }
       else { c = e & (B - 1); i = e >> logB; }
-      const V v = load_as<V>(p.in, ib + (int64_t)(s0 + c) * p.in_ss + (int64_t)i * p.in_es,
-                             p.in_kind);
+      V v = load_as<V>(p.in, ib + (int64_t)(s0 + c) * p.in_ss + (int64_t)i * p.in_es,
+                       p.in_kind);
+      if (neg) v = vconj(v);
       const int pos = FFT ? bitrev(i, logL) : i;
       tile[lds_addr(pos * B + c)] = v;
     }
@@ -67,7 +70,8 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
       const int i = k >> p.logN1;
       const int c = (k & mask1) - s0;
       if (c >= 0 && c < B) {
-        const V v = load_as<V>(p.taps_x, (int64_t)inst * p.inst_taps_x + e, p.in_kind);
+        V v = load_as<V>(p.taps_x, (int64_t)inst * p.inst_taps_x + e, p.in_kind);
+        if (neg) v = vconj(v);
         const int pos = FFT ? bitrev(i, logL) : i;
         tile[lds_addr(pos * B + c)] = v;
       }
@@ -89,7 +93,8 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
       const int k = ek[e];
       const int i = k >> p.logN1;
       const int c = (k & mask1) - s0;
-      const V v = (p.in_mode == IN_SPARSE_ONES) ? vone<V>() : load_as<V>(p.in, ib + e, p.in_kind);
+      V v = (p.in_mode == IN_SPARSE_ONES) ? vone<V>() : load_as<V>(p.in, ib + e, p.in_kind);
+      if (neg) v = vconj(v);
       const int pos = FFT ? bitrev(i, logL) : i;
       tile[lds_addr(pos * B + c)] = v;
     }
@@ -97,7 +102,7 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   __syncthreads();
 
   // ---- transform
-  lds_transform<FFT>(tile, L, logL, B, logB, twlo, twhi, p.twS, p.logN, p.sign);
+  lds_fft<FFT>(tile, L, logL, B, logB, (const V*)p.tws);
 
   // ---- residual output: r = y - (S_Omega U s) at the rows of Phi this
   // workgroup produced (forward transform of the support, Algorithm 1.1 step 7)
@@ -116,7 +121,9 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
       int c, j;
       if (p.out_es == 1) { j = k & (L - 1); c = (k >> logL) - s0; }
       else { c = (k & esmask) - s0; j = k >> p.log_out_es; }
-      const V v = vscale(tile[lds_addr(j * B + c)], p.scale);
+      V v = tile[lds_addr(j * B + c)];
+      if (neg) v = vconj(v);
+      v = vscale(v, p.scale);
       const int64_t q = pos1 ? (int64_t)pos1[e] : (int64_t)e;
       const V yv = load_as<V>(p.yres, (int64_t)inst * p.inst_yres + q, p.yres_kind);
       store_as(p.rout, (int64_t)inst * p.inst_rout + q, p.r_kind, vsub(yv, v));
@@ -148,6 +155,7 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
     if (p.out_es == 1) { c = e >> logL; j = e & (L - 1); }
     else { c = e & (B - 1); j = e >> logB; }
     V v = tile[lds_addr(j * B + c)];
+    if (neg) v = vconj(v);
     if constexpr (FFT) {
       if (p.inter_tw) {
         const uint32_t q = ((uint32_t)(s0 + c) * (uint32_t)j) & (uint32_t)(p.N - 1);
@@ -181,7 +189,7 @@ size_t xform_lds_bytes(int vk, bool fft, const XParams& p) {
   const size_t vb = vbytes(vk);
   const size_t tile_n = (size_t)p.B * p.L;
   const size_t tile_alloc = tile_n + (tile_n >> 5) + 1;
-  const size_t ntw = fft ? ((size_t)1 << p.twS) + ((size_t)p.N >> p.twS) : 0;
+  const size_t ntw = (fft && p.inter_tw) ? ((size_t)1 << p.twS) + ((size_t)p.N >> p.twS) : 0;
   size_t bytes = (tile_alloc + ntw) * vb;
   bytes = (bytes + 15) & ~(size_t)15;
   bytes += 16 * sizeof(Sel);

@@ -136,6 +136,30 @@ __device__ __forceinline__ void dit_const(V* x) {
   }
 }
 
+// The transposed network (decimation in frequency): levels from the largest
+// span down, pairs (m, m + 2^s) -> (a + b, w (a - b)); natural-order input,
+// bit-reversed output within the block.
+template <int S, int s, int M, class V>
+__device__ __forceinline__ void dif_cpairs(V* x) {
+  if constexpr (M < (1 << S)) {
+    constexpr int half = 1 << s;
+    if constexpr ((M & half) == 0) {
+      const V a = x[M], b = x[M + half];
+      x[M] = vadd(a, b);
+      x[M + half] = twp<s, (M & (half - 1))>(vsub(a, b));
+    }
+    dif_cpairs<S, s, M + 1>(x);
+  }
+}
+
+template <int S, int s, class V>
+__device__ __forceinline__ void dif_const(V* x) {
+  if constexpr (s >= 0) {
+    dif_cpairs<S, s, 0>(x);
+    dif_const<S, s - 1>(x);
+  }
+}
+
 template <int S, int s, int M, class V>
 __device__ __forceinline__ void wht_pairs(V* x) {
   if constexpr (M < (1 << S)) {
@@ -170,7 +194,7 @@ __device__ __forceinline__ double2 vconj(double2 v) { return make_double2(v.x, -
 // constant-twiddle DIT network (in-place decimation-in-time DFT on
 // bit-reversed input).  Hadamard: the natural-order WHT butterflies.
 // Element (i, c) of the tile lives at lds_addr(i*B + c).
-template <int S, bool FFT, class V>
+template <int S, bool FFT, bool DIF, class V>
 __device__ __forceinline__ void fft_stage(V* t, int L, int B, int logB, int logh, const V* tws) {
   constexpr int R = 1 << S;
   const int h = 1 << logh;
@@ -196,7 +220,7 @@ __device__ __forceinline__ void fft_stage(V* t, int L, int B, int logB, int logh
     V x[R];
 #pragma unroll
     for (int m = 0; m < R; ++m) x[m] = t[a[m]];
-    if constexpr (FFT) {
+    if constexpr (FFT && !DIF) {
       if constexpr (S == 4) {
         if (logh > 0) {
           const V* tk = tws + stage_tw_offset(h) + 15 * k - 1;
@@ -205,6 +229,16 @@ __device__ __forceinline__ void fft_stage(V* t, int L, int B, int logB, int logh
         }
       }
       dit_const<S, 0>(x);
+    } else if constexpr (FFT) {
+      // transposed stage: network first, then the same per-register twiddles
+      dif_const<S, S - 1>(x);
+      if constexpr (S == 4) {
+        if (logh > 0) {
+          const V* tk = tws + stage_tw_offset(h) + 15 * k - 1;
+#pragma unroll
+          for (int m = 1; m < R; ++m) x[m] = cmul(x[m], tk[m]);
+        }
+      }
     } else {
       wht_block<S, 0>(x);
     }
@@ -214,21 +248,34 @@ __device__ __forceinline__ void fft_stage(V* t, int L, int B, int logB, int logh
   __syncthreads();
 }
 
-// B interleaved length-L transforms in LDS with the + sign: Fourier input
-// placed in bit-reversed order (position bitrev(i) of each sequence), output
-// in natural order; Hadamard natural in and out.  A radix-2^(logL mod 4)
-// stage at span 1, then radix-16 stages; tws is the per-span twiddle table
-// (spans up to L/16; unused for Hadamard).  Ends with a barrier.
-template <bool FFT, class V>
+// B interleaved length-L transforms in LDS with the + sign.  Fourier,
+// DIF = false: input placed in bit-reversed order (position bitrev(i) of each
+// sequence), output in natural order -- a radix-2^(logL mod 4) stage at span
+// 1, then radix-16 stages.  DIF = true (the transposed algorithm): natural
+// input, output at position bitrev(j) -- the same stages in reverse order,
+// each transposed.  Hadamard: natural in and out either way.  tws is the
+// per-span twiddle table (spans up to L/16; unused for Hadamard).  Ends with
+// a barrier.
+template <bool FFT, bool DIF, class V>
 __device__ __forceinline__ void lds_fft(V* t, int L, int logL, int B, int logB, const V* tws) {
-  int logh = logL & 3;
-  switch (logh) {
-    case 1: fft_stage<1, FFT>(t, L, B, logB, 0, tws); break;
-    case 2: fft_stage<2, FFT>(t, L, B, logB, 0, tws); break;
-    case 3: fft_stage<3, FFT>(t, L, B, logB, 0, tws); break;
-    default: break;
+  const int r = logL & 3;
+  if constexpr (!DIF || !FFT) {
+    switch (r) {
+      case 1: fft_stage<1, FFT, false>(t, L, B, logB, 0, tws); break;
+      case 2: fft_stage<2, FFT, false>(t, L, B, logB, 0, tws); break;
+      case 3: fft_stage<3, FFT, false>(t, L, B, logB, 0, tws); break;
+      default: break;
+    }
+    for (int logh = r; logh < logL; logh += 4) fft_stage<4, FFT, false>(t, L, B, logB, logh, tws);
+  } else {
+    for (int logh = logL - 4; logh >= r; logh -= 4) fft_stage<4, true, true>(t, L, B, logB, logh, tws);
+    switch (r) {
+      case 1: fft_stage<1, true, true>(t, L, B, logB, 0, tws); break;
+      case 2: fft_stage<2, true, true>(t, L, B, logB, 0, tws); break;
+      case 3: fft_stage<3, true, true>(t, L, B, logB, 0, tws); break;
+      default: break;
+    }
   }
-  for (; logh < logL; logh += 4) fft_stage<4, FFT>(t, L, B, logB, logh, tws);
 }
 
 }  // namespace fcmp

@@ -234,7 +234,7 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
         }
       }
       __syncthreads();
-      lds_fft<F>(tile, N, logN, 1, 0, stage_tw<V>(p));
+      lds_fft<F, false>(tile, N, logN, 1, 0, stage_tw<V>(p));
       for (int j = tid; j < N; j += WG_THREADS) {
         if ((s.excl[j >> 5] >> (j & 31)) & 1u) continue;
         const double kk2 = vmag2(vscale(tile[lds_addr(j)], inv_sqrt_n));

@@ -13,10 +13,21 @@
 
 namespace fcmp {
 
-// ROLE only names the launch for profilers: 0 one workgroup per transform,
-// 1 first pass (columns), 2 second pass (rows).
+// Identification key type: |h|^2 in the correlation precision.
+template <class V> struct KeyOf { using T = double; };
+template <> struct KeyOf<float> { using T = float; };
+template <> struct KeyOf<float2> { using T = float; };
+__device__ __forceinline__ float kmag2(float v) { return v * v; }
+__device__ __forceinline__ float kmag2(float2 v) { return v.x * v.x + v.y * v.y; }
+__device__ __forceinline__ double kmag2(double v) { return v * v; }
+__device__ __forceinline__ double kmag2(double2 v) { return v.x * v.x + v.y * v.y; }
+
+// ROLE: 0 one workgroup per transform, 1 first pass (columns), 2 second pass
+// (rows; dense input, so the Fourier core runs transposed: natural input,
+// bit-reversed output positions).
 template <class V, bool FFT, int ROLE>
 __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
+  constexpr bool DIF = FFT && ROLE == 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int inst = blockIdx.y;
   if (p.status && p.status[inst].done) return;
@@ -37,25 +48,50 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   Sel* red = (Sel*)(((uintptr_t)(twhi + nhi) + 15) & ~(uintptr_t)15);
   const bool neg = p.sign < 0;   // conj(F(conj x)): the core runs with the + sign
 
+  // Global loads are issued XU at a time (from clamped, always valid
+  // addresses) before their LDS writes, so each thread waits for memory once
+  // per batch rather than once per element.
+  constexpr int XU = sizeof(V) >= 16 ? 4 : 8;
   if (itw) {
     const V* glo = (const V*)p.tw_lo;
     const V* ghi = (const V*)p.tw_hi;
-    for (int e = tid; e < nlo; e += nt) twlo[e] = glo[e];
-    for (int e = tid; e < nhi; e += nt) twhi[e] = ghi[e];
+    const int ntw = nlo + nhi;
+    for (int e0 = tid; e0 < ntw; e0 += nt * XU) {
+      V w[XU];
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int e = min(e0 + u * nt, ntw - 1);
+        w[u] = e < nlo ? glo[e] : ghi[e - nlo];
+      }
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int e = e0 + u * nt;
+        if (e < ntw) twlo[e] = w[u];   // twhi follows twlo contiguously
+      }
+    }
   }
 
   // ---- load
   if (p.in_mode == IN_DENSE) {
     const int64_t ib = (int64_t)inst * p.inst_in;
-    for (int e = tid; e < tile_n; e += nt) {
-      int c, i;
-      if (p.in_es == 1) { c = e >> logL; i = e & (L - 1); }
-      else { c = e & (B - 1); i = e >> logB; }
-      V v = load_as<V>(p.in, ib + (int64_t)(s0 + c) * p.in_ss + (int64_t)i * p.in_es,
-                       p.in_kind);
-      if (neg) v = vconj(v);
-      const int pos = FFT ? bitrev(i, logL) : i;
-      tile[lds_addr(pos * B + c)] = v;
+    for (int e0 = tid; e0 < tile_n; e0 += nt * XU) {
+      V v[XU];
+      int a[XU];
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int e = min(e0 + u * nt, tile_n - 1);
+        int c, i;
+        if (p.in_es == 1) { c = e >> logL; i = e & (L - 1); }
+        else { c = e & (B - 1); i = e >> logB; }
+        v[u] = load_as<V>(p.in, ib + (int64_t)(s0 + c) * p.in_ss + (int64_t)i * p.in_es,
+                          p.in_kind);
+        const int pos = (FFT && !DIF) ? bitrev(i, logL) : i;
+        a[u] = lds_addr(pos * B + c);
+      }
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        if (e0 + u * nt < tile_n) tile[a[u]] = neg ? vconj(v[u]) : v[u];
+      }
     }
   } else if (p.in_mode == IN_TAPS) {
     // zero-filled sparse vector S_Lambda^T x: this workgroup keeps the taps
@@ -65,15 +101,27 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
     __syncthreads();
     const int32_t* tl = p.taps_lam + (int64_t)inst * p.inst_taps_lam;
     const int mask1 = (1 << p.logN1) - 1;
-    for (int e = tid; e < p.ntaps; e += nt) {
-      const int k = tl[e];
-      const int i = k >> p.logN1;
-      const int c = (k & mask1) - s0;
-      if (c >= 0 && c < B) {
-        V v = load_as<V>(p.taps_x, (int64_t)inst * p.inst_taps_x + e, p.in_kind);
-        if (neg) v = vconj(v);
-        const int pos = FFT ? bitrev(i, logL) : i;
-        tile[lds_addr(pos * B + c)] = v;
+    for (int e0 = tid; e0 < p.ntaps; e0 += nt * XU) {
+      int kk[XU];
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int e = e0 + u * nt;
+        kk[u] = tl[min(e, p.ntaps - 1)];
+        if (e >= p.ntaps) kk[u] = -1;
+      }
+      V v[XU];
+#pragma unroll
+      for (int u = 0; u < XU; ++u)
+        v[u] = load_as<V>(p.taps_x, (int64_t)inst * p.inst_taps_x + min(e0 + u * nt, p.ntaps - 1),
+                          p.in_kind);
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int c = (kk[u] & mask1) - s0;
+        if (kk[u] >= 0 && c >= 0 && c < B) {
+          const int i = kk[u] >> p.logN1;
+          const int pos = FFT ? bitrev(i, logL) : i;
+          tile[lds_addr(pos * B + c)] = neg ? vconj(v[u]) : v[u];
+        }
       }
     }
   } else {
@@ -89,20 +137,31 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
     const int32_t* ek = p.ent_k + (int64_t)inst * p.inst_ent;
     const int mask1 = (1 << p.logN1) - 1;
     const int64_t ib = (int64_t)inst * p.inst_in;
-    for (int e = lo + tid; e < hi; e += nt) {
-      const int k = ek[e];
-      const int i = k >> p.logN1;
-      const int c = (k & mask1) - s0;
-      V v = (p.in_mode == IN_SPARSE_ONES) ? vone<V>() : load_as<V>(p.in, ib + e, p.in_kind);
-      if (neg) v = vconj(v);
-      const int pos = FFT ? bitrev(i, logL) : i;
-      tile[lds_addr(pos * B + c)] = v;
+    const bool ones = p.in_mode == IN_SPARSE_ONES;
+    for (int e0 = lo + tid; e0 < hi; e0 += nt * XU) {
+      int kk[XU];
+      V v[XU];
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int e = min(e0 + u * nt, hi - 1);
+        kk[u] = ek[e];
+        v[u] = ones ? vone<V>() : load_as<V>(p.in, ib + e, p.in_kind);
+      }
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        if (e0 + u * nt < hi) {
+          const int i = kk[u] >> p.logN1;
+          const int c = (kk[u] & mask1) - s0;
+          const int pos = FFT ? bitrev(i, logL) : i;
+          tile[lds_addr(pos * B + c)] = neg ? vconj(v[u]) : v[u];
+        }
+      }
     }
   }
   __syncthreads();
 
   // ---- transform
-  lds_fft<FFT>(tile, L, logL, B, logB, (const V*)p.tws);
+  lds_fft<FFT, DIF>(tile, L, logL, B, logB, (const V*)p.tws);
 
   // ---- residual output: r = y - (S_Omega U s) at the rows of Phi this
   // workgroup produced (forward transform of the support, Algorithm 1.1 step 7)
@@ -116,24 +175,42 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
     const int32_t* ek = p.ent2_k + (int64_t)inst * p.inst_ent2;
     const int32_t* pos1 = p.pos1 ? p.pos1 + (int64_t)inst * p.inst_ent2 : nullptr;
     const int esmask = (1 << p.log_out_es) - 1;
-    for (int e = lo + tid; e < hi; e += nt) {
-      const int k = ek[e];
-      int c, j;
-      if (p.out_es == 1) { j = k & (L - 1); c = (k >> logL) - s0; }
-      else { c = (k & esmask) - s0; j = k >> p.log_out_es; }
-      V v = tile[lds_addr(j * B + c)];
-      if (neg) v = vconj(v);
-      v = vscale(v, p.scale);
-      const int64_t q = pos1 ? (int64_t)pos1[e] : (int64_t)e;
-      const V yv = load_as<V>(p.yres, (int64_t)inst * p.inst_yres + q, p.yres_kind);
-      store_as(p.rout, (int64_t)inst * p.inst_rout + q, p.r_kind, vsub(yv, v));
+    constexpr int RU = sizeof(V) >= 16 ? 2 : 4;
+    for (int e0 = lo + tid; e0 < hi; e0 += nt * RU) {
+      int kk[RU], qq[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int e = min(e0 + u * nt, hi - 1);
+        kk[u] = ek[e];
+        qq[u] = pos1 ? pos1[e] : e;
+      }
+      V yv[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u)
+        yv[u] = load_as<V>(p.yres, (int64_t)inst * p.inst_yres + qq[u], p.yres_kind);
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        if (e0 + u * nt < hi) {
+          const int k = kk[u];
+          int c, j;
+          if (p.out_es == 1) { j = k & (L - 1); c = (k >> logL) - s0; }
+          else { c = (k & esmask) - s0; j = k >> p.log_out_es; }
+          V v = tile[lds_addr((DIF ? bitrev(j, logL) : j) * B + c)];
+          if (neg) v = vconj(v);
+          v = vscale(v, p.scale);
+          store_as(p.rout, (int64_t)inst * p.inst_rout + qq[u], p.r_kind, vsub(yv[u], v));
+        }
+      }
     }
     return;
   }
 
-  // ---- store / identify
-  double bkey = -1.0;
-  int64_t bidx = -1;
+  // ---- store / identify (keys |v|^2 unscaled in the transform precision;
+  // the winner's key is scaled once at the end)
+  using KT = typename KeyOf<V>::T;
+  KT bkey = (KT)-1;
+  int bidx = -1;
+  const bool store = p.out_kind >= 0 || p.out2_kind >= 0;
   const uint32_t* excl = p.excl ? p.excl + (int64_t)inst * p.inst_excl : nullptr;
   // stage the exclusion bits this workgroup needs
   uint32_t* xw = (uint32_t*)(red + 16);
@@ -150,11 +227,21 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
     }
     __syncthreads();
   }
+  const int out_ss = (int)p.out_ss, out_es = (int)p.out_es;
   for (int e = tid; e < tile_n; e += nt) {
-    int c, j;
-    if (p.out_es == 1) { c = e >> logL; j = e & (L - 1); }
-    else { c = e & (B - 1); j = e >> logB; }
-    V v = tile[lds_addr(j * B + c)];
+    int c, j, pos;
+    if (out_es == 1) {
+      c = e >> logL; j = e & (L - 1);
+      pos = DIF ? bitrev(j, logL) : j;
+    } else {
+      c = e & (B - 1);
+      const int q = e >> logB;
+      // transposed core: walk the LDS positions (conflict-free) unless the
+      // values are stored, then walk the outputs (coalesced)
+      if (DIF && !store) { pos = q; j = bitrev(q, logL); }
+      else { j = q; pos = DIF ? bitrev(q, logL) : q; }
+    }
+    V v = tile[lds_addr(pos * B + c)];
     if (neg) v = vconj(v);
     if constexpr (FFT) {
       if (p.inter_tw) {
@@ -162,10 +249,12 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
         v = cmul(v, tw_lookup(twlo, twhi, q, p.twS, p.sign));
       }
     }
-    v = vscale(v, p.scale);
-    const int64_t o = (int64_t)(s0 + c) * p.out_ss + (int64_t)j * p.out_es;
-    if (p.out_kind >= 0) store_as(p.out, (int64_t)inst * p.inst_out + o, p.out_kind, v);
-    if (p.out2_kind >= 0) store_as(p.out2, (int64_t)inst * p.inst_out2 + o, p.out2_kind, v);
+    const int o = (s0 + c) * out_ss + j * out_es;   // < N <= 2^24
+    if (store) {
+      const V vs = vscale(v, p.scale);
+      if (p.out_kind >= 0) store_as(p.out, (int64_t)inst * p.inst_out + o, p.out_kind, vs);
+      if (p.out2_kind >= 0) store_as(p.out2, (int64_t)inst * p.inst_out2 + o, p.out2_kind, vs);
+    }
     if (p.partial) {
       bool ex = false;
       if (excl) {
@@ -174,13 +263,14 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
         else ex = bit_is_set(excl, o);
       }
       if (!ex) {
-        const double kk = vmag2(v);
-        if (sel_better(kk, o, bkey, bidx)) { bkey = kk; bidx = o; }
+        const KT kk = kmag2(v);
+        if (kk > bkey || (kk == bkey && (unsigned)o < (unsigned)bidx)) { bkey = kk; bidx = o; }
       }
     }
   }
   if (p.partial) {
-    const Sel r = block_sel_reduce(bkey, bidx, red);
+    const double key = bidx >= 0 ? (double)bkey * (p.scale * p.scale) : -1.0;
+    const Sel r = block_sel_reduce(key, (int64_t)bidx, red);
     if (tid == 0) p.partial[(int64_t)inst * p.inst_part + g] = r;
   }
 }

@@ -306,6 +306,17 @@ def main():
         methods[meth] = {"ms_per_step": round(t * 1e3, 3), "solves_per_s": round(B / t, 3)}
         print(f"[bench] {meth}: {t*1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
+    # ---- adaptive with the switch iteration measured by the autotuner
+    model_t, _ = fc.adaptive_switch("F", N, "fp32")
+    tuned_t = fc.autotune("F", N, M, "fp32", batch=16, device=dev)
+    if args.steps > 0:
+        t = time_steps(lambda: plan.solve(ys, method="adaptive"), args.steps, 1)
+        methods["adaptive_tuned"] = {"ms_per_step": round(t * 1e3, 3),
+                                     "solves_per_s": round(B / t, 3),
+                                     "switch_t": tuned_t, "model_switch_t": model_t}
+        print(f"[bench] adaptive (tuned switch {tuned_t}, model {model_t}): {t*1e3:.2f} ms/step",
+              file=sys.stderr, flush=True)
+
     # ---- plain single-instance path (fcmp_solve per instance)
     lat = []
     for i in range(min(args.plain, B)):

@@ -268,6 +268,34 @@ int fcmp_server_get_info(fcmp_server* srv, fcmp_server_info* info);
  * objects; the pool may be reused once it returns. */
 int fcmp_server_destroy(fcmp_server* srv);
 
+/* ---- adaptive switch autotuning ---------------------------------------- */
+
+/* The adaptive method (FCMP_CORR_ADAPTIVE with switch_t = 0) uses the fast
+ * correlation up to a switch iteration.  Without tuning that iteration is the
+ * flop-model crossover of Table I (Fourier: 2 + floor(5 log2 N / 6);
+ * Hadamard: 1 + log2 N).  fcmp_autotune measures it instead: it builds a
+ * lockstep plan of `batch` problems of (class, N, M) in the workspace
+ * (bytes from fcmp_autotune_query_workspace, host-only), times the fast and
+ * the conventional correlation launch sequences at growing tap counts on the
+ * stream, and records the last iteration at which the fast one is no slower
+ * in the library's process-wide table; *switch_t receives it.  cache_path
+ * (nullable): a text file of "class N precision switch_t" lines; an entry for
+ * (class, N, precision) found there is used without measuring, and a new
+ * measurement is appended.  The call synchronises the stream. */
+int fcmp_autotune_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
+                                  int32_t corr_precision, int32_t batch, size_t* bytes);
+int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
+                  int32_t batch, const char* cache_path, void* ws_dev, size_t ws_bytes,
+                  int32_t* switch_t, void* hip_stream);
+/* Loads every valid entry of a cache file into the table (host-only);
+ * FCMP_E_NOTFOUND when the file is missing or holds no valid entry. */
+int fcmp_autotune_load(const char* cache_path);
+/* The switch iteration an adaptive solve with switch_t = 0 uses; *tuned
+ * (nullable) is 1 when it comes from the table, 0 for the flop model.
+ * Host-only. */
+int fcmp_adaptive_switch(int32_t matrix_class, int64_t N, int32_t corr_precision,
+                         int32_t* switch_t, int32_t* tuned);
+
 /* ---- phase timing ------------------------------------------------------ */
 
 /* When enabled, every launch sequence of a phase is bracketed by hipEvents on

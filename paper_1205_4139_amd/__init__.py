@@ -105,6 +105,12 @@ def _load():
                                    ctypes.POINTER(Stats), vp], ctypes.c_int),
         "fcmp_batch_plan_destroy": ([vp], ctypes.c_int),
         "fcmp_plan_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_autotune_query_workspace": ([i32, i64, i64, i32, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_autotune": ([i32, i64, i64, i32, i32, ctypes.c_char_p, vp, sz,
+                           ctypes.POINTER(i32), vp], ctypes.c_int),
+        "fcmp_autotune_load": ([ctypes.c_char_p], ctypes.c_int),
+        "fcmp_adaptive_switch": ([i32, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+                                 ctypes.c_int),
         "fcmp_server_footprint": ([P, O, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_server_create": ([ctypes.POINTER(vp), vp, sz, ctypes.POINTER(ServerConfig)],
                                ctypes.c_int),
@@ -516,3 +522,29 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def autotune(cls, N, M, precision="fp32", batch=8, cache_path=None, device="cuda") -> int:
+    """Measures the adaptive switch iteration for (class, N, precision) on the
+    device and records it for later adaptive solves; returns it."""
+    nb = ctypes.c_size_t(0)
+    _check(lib.fcmp_autotune_query_workspace(CLASS[cls], int(N), int(M), PREC[precision],
+                                             int(batch), ctypes.byref(nb)))
+    ws = _workspace(nb.value, device)
+    t = ctypes.c_int32(0)
+    _check(lib.fcmp_autotune(CLASS[cls], int(N), int(M), PREC[precision], int(batch),
+                             cache_path.encode() if cache_path else None, _ptr(ws), ws.numel(),
+                             ctypes.byref(t), _stream()))
+    return t.value
+
+
+def autotune_load(cache_path) -> None:
+    _check(lib.fcmp_autotune_load(str(cache_path).encode()))
+
+
+def adaptive_switch(cls, N, precision="fp32") -> tuple:
+    """(switch iteration used by adaptive solves with switch_t = 0, tuned?)."""
+    t, tuned = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib.fcmp_adaptive_switch(CLASS[cls], int(N), PREC[precision], ctypes.byref(t),
+                                    ctypes.byref(tuned)))
+    return t.value, bool(tuned.value)

@@ -1,0 +1,187 @@
+// Autotuner for the adaptive correlation method.
+//
+// The paper's adaptive strategy runs the fast method while it is cheaper
+// than the conventional one and switches afterwards; Table I's flop counts
+// put the crossover at 6(t-1) = 5 log2 N (Fourier) and t-1 = log2 N
+// (Hadamard).  On the device the two costs are not flop counts: the fast
+// method is a gather stream over the kernel vector and the conventional one
+// a residual plus a two-pass transform, so the crossover is measured here,
+// per (class, N, precision), by timing both correlation launch sequences of
+// a lockstep plan at growing tap counts, and stored in the library's table
+// (and optionally a text cache, one "class N precision switch_t" per line).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "plan.h"
+
+using namespace fcmp;
+
+namespace {
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return set_error(FCMP_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+constexpr int kReps = 4;
+
+int tune_shape(int32_t cls, int64_t N, int64_t M, int32_t batch, int32_t tmax,
+               std::vector<int32_t>& omega, std::vector<fcmp_problem>& probs, fcmp_options& opt,
+               int32_t precision) {
+  if (cls != FCMP_HADAMARD && cls != FCMP_FOURIER) return set_error(FCMP_E_INVALID, "bad class");
+  if (M < 2 || M > N) return set_error(FCMP_E_INVALID, "M must be in [2, N]");
+  if (batch < 1 || batch > 4096) return set_error(FCMP_E_INVALID, "batch must be in [1, 4096]");
+  // rows spread evenly over [0, N): the costs do not depend on which rows
+  omega.resize((size_t)M);
+  for (int64_t m = 0; m < M; ++m) omega[(size_t)m] = (int32_t)((m * N) / M);
+  fcmp_problem p{};
+  p.matrix_class = cls;
+  p.N = N;
+  p.M = M;
+  p.K = std::min<int64_t>(tmax, M - 1);
+  p.omega = omega.data();
+  probs.assign((size_t)batch, p);
+  opt = fcmp_options{};
+  opt.algorithm = FCMP_OMP;
+  opt.corr_method = FCMP_CORR_ADAPTIVE;
+  opt.corr_precision = precision;
+  return FCMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fcmp_autotune_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
+                                  int32_t corr_precision, int32_t batch, size_t* bytes) {
+  if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
+  std::vector<int32_t> om;
+  std::vector<fcmp_problem> probs;
+  fcmp_options opt;
+  int rc = tune_shape(matrix_class, N, M, batch, model_switch_t(matrix_class, N) * 8 + 8, om,
+                      probs, opt, corr_precision);
+  if (rc) return rc;
+  fcmp_plan P;
+  if ((rc = plan_init(P, batch, probs.data(), &opt))) return rc;
+  *bytes = P.total;
+  return FCMP_OK;
+}
+
+int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
+                  int32_t batch, const char* cache_path, void* ws_dev, size_t ws_bytes,
+                  int32_t* switch_t, void* hip_stream) {
+  if (!switch_t) return set_error(FCMP_E_INVALID, "switch_t is NULL");
+  const int tmax = model_switch_t(matrix_class, N) * 8 + 8;
+  std::vector<int32_t> om;
+  std::vector<fcmp_problem> probs;
+  fcmp_options opt;
+  int rc = tune_shape(matrix_class, N, M, batch, tmax, om, probs, opt, corr_precision);
+  if (rc) return rc;
+  if (cache_path && fcmp_autotune_load(cache_path) == FCMP_OK) {
+    int t = 0;
+    if (tuned_switch(matrix_class, N, corr_precision, &t)) {
+      *switch_t = t;
+      return FCMP_OK;
+    }
+  }
+  fcmp_plan P;
+  if ((rc = plan_init(P, batch, probs.data(), &opt))) return rc;
+  if (!ws_dev) return set_error(FCMP_E_INVALID, "workspace is NULL");
+  if (ws_bytes < P.total) return set_error(FCMP_E_WORKSPACE, "workspace too small");
+  hipStream_t st = (hipStream_t)hip_stream;
+  plan_layout(P, (char*)ws_dev);
+  if ((rc = plan_build(P, probs.data(), st))) return rc;
+  // taps: distinct columns (odd stride), unit coefficients; y = 0
+  const bool F = matrix_class == FCMP_FOURIER;
+  const size_t wb = F ? 16 : 8;
+  std::vector<int32_t> lam((size_t)(batch * P.sK), 0);
+  std::vector<double> x((size_t)(batch * P.sK) * (wb / 8), 0.0);
+  for (int64_t b = 0; b < batch; ++b)
+    for (int64_t k = 0; k < P.shape.K; ++k) {
+      lam[(size_t)(b * P.sK + k)] = (int32_t)((k * 40503 + 17) & (N - 1));
+      x[(size_t)(b * P.sK + k) * (wb / 8)] = 1.0;
+    }
+  HIP_TRY(hipMemcpyAsync(P.lam, lam.data(), lam.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.x, x.data(), x.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)P.y_ent, 0u, (int64_t)(batch * P.sM * wb / 4), st));
+  HIP_TRY(launch_fill_u32(P.excl, 0u, batch * P.sE, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)P.h0, 0u, (int64_t)(batch * P.sN * wb / 4), st));
+  HIP_TRY(launch_init_status(P.status, P.y_ent, (int)M, F, P.sM, batch, st));
+  hipEvent_t e0, e1, e2;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventCreate(&e2));
+  int npart = 0;
+  // warm up both paths
+  if ((rc = plan_fast_corr(P, 2, &npart, st)) || (rc = plan_conv_corr(P, 2, &npart, st))) {
+    hipEventDestroy(e0); hipEventDestroy(e1); hipEventDestroy(e2);
+    return rc;
+  }
+  int best = 1;
+  for (int t = 2; t <= P.shape.K; t += std::max(1, (t - 1) / 4)) {
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < kReps && !rc; ++r) rc = plan_fast_corr(P, t, &npart, st);
+    (void)hipEventRecord(e1, st);
+    for (int r = 0; r < kReps && !rc; ++r) rc = plan_conv_corr(P, t, &npart, st);
+    (void)hipEventRecord(e2, st);
+    if (rc) break;
+    if (hipEventSynchronize(e2) != hipSuccess) { rc = set_error(FCMP_E_DEVICE, "event sync"); break; }
+    float fast_ms = 0.f, conv_ms = 0.f;
+    (void)hipEventElapsedTime(&fast_ms, e0, e1);
+    (void)hipEventElapsedTime(&conv_ms, e1, e2);
+    if (fast_ms <= conv_ms) best = t;
+    else break;   // the fast cost only grows with t
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipEventDestroy(e2);
+  if (rc) return rc;
+  set_tuned_switch(matrix_class, N, corr_precision, best);
+  *switch_t = best;
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%d %lld %d %d\n", matrix_class, (long long)N, corr_precision, best);
+      std::fclose(f);
+    } else {
+      return set_error(FCMP_E_INVALID, "cannot append to the cache file");
+    }
+  }
+  return FCMP_OK;
+}
+
+int fcmp_autotune_load(const char* cache_path) {
+  if (!cache_path) return set_error(FCMP_E_INVALID, "cache_path is NULL");
+  FILE* f = std::fopen(cache_path, "r");
+  if (!f) return set_error(FCMP_E_NOTFOUND, "no cache file");
+  int cls = 0, prec = 0, t = 0;
+  long long N = 0;
+  int n = 0;
+  while (std::fscanf(f, "%d %lld %d %d", &cls, &N, &prec, &t) == 4) {
+    if ((cls == FCMP_HADAMARD || cls == FCMP_FOURIER) && N >= 2 && (N & (N - 1)) == 0 &&
+        (prec == FCMP_FP64 || prec == FCMP_FP32) && t >= 1) {
+      set_tuned_switch(cls, N, prec, t);
+      ++n;
+    }
+  }
+  std::fclose(f);
+  return n > 0 ? FCMP_OK : set_error(FCMP_E_NOTFOUND, "no valid entries in the cache file");
+}
+
+int fcmp_adaptive_switch(int32_t matrix_class, int64_t N, int32_t corr_precision,
+                         int32_t* switch_t, int32_t* tuned) {
+  if (!switch_t) return set_error(FCMP_E_INVALID, "switch_t is NULL");
+  if (matrix_class != FCMP_HADAMARD && matrix_class != FCMP_FOURIER)
+    return set_error(FCMP_E_INVALID, "bad class");
+  if (N < 2 || (N & (N - 1)) != 0) return set_error(FCMP_E_INVALID, "N must be a power of two");
+  int t = 0;
+  const bool have = tuned_switch(matrix_class, N, corr_precision, &t);
+  *switch_t = have ? t : model_switch_t(matrix_class, N);
+  if (tuned) *tuned = have ? 1 : 0;
+  return FCMP_OK;
+}
+
+}  // extern "C"

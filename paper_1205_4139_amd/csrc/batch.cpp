@@ -196,7 +196,7 @@ int wg_build(WgBatch& B, const fcmp_problem* probs, hipStream_t st) {
       d.K = (int)p.K;
       d.method = B.opt.corr_method;
       d.switch_t = B.opt.switch_t > 0 ? B.opt.switch_t
-                                      : (F ? 2 + (5 * G.g.logN) / 6 : 1 + G.g.logN);
+                                      : default_switch_t(G.cls, G.N, B.opt.corr_precision);
       d.pad = 0;
       d.off_om = (const char*)(G.ent_k + k * G.sM) - base;
       d.off_y = ((const char*)G.y_ent + k * G.sM * vbytes(wk)) - base;

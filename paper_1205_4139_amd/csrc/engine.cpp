@@ -5,6 +5,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace fcmp {
 
@@ -23,6 +26,35 @@ static int ilog2(int64_t n) {
 }
 
 bool single_ok(int vk, int N) { return (size_t)N * vbytes(vk) <= 131072; }
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int64_t, int>, int> g_switch;
+}  // namespace
+
+int model_switch_t(int matrix_class, int64_t N) {
+  const int logN = ilog2(N);
+  return matrix_class == FCMP_FOURIER ? 2 + (5 * logN) / 6 : 1 + logN;
+}
+
+void set_tuned_switch(int matrix_class, int64_t N, int precision, int switch_t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_switch[std::make_tuple(matrix_class, N, precision)] = switch_t;
+}
+
+bool tuned_switch(int matrix_class, int64_t N, int precision, int* switch_t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_switch.find(std::make_tuple(matrix_class, N, precision));
+  if (it == g_switch.end()) return false;
+  *switch_t = it->second;
+  return true;
+}
+
+int default_switch_t(int matrix_class, int64_t N, int precision) {
+  int t = 0;
+  if (tuned_switch(matrix_class, N, precision, &t)) return t;
+  return model_switch_t(matrix_class, N);
+}
 
 Geo make_geo(bool fourier, int N) {
   Geo g;

@@ -42,6 +42,14 @@ struct Tune {
 const Tune& tune();
 
 bool single_ok(int vk, int N);
+// Last iteration of the adaptive method that uses the fast correlation: the
+// autotuned crossover for (class, N, precision) when one was measured or
+// loaded, else the flop model of Table I (fast while 6(t-1) < 5 log2 N for
+// Fourier, t-1 < log2 N for Hadamard).
+int default_switch_t(int matrix_class, int64_t N, int precision);
+int model_switch_t(int matrix_class, int64_t N);
+void set_tuned_switch(int matrix_class, int64_t N, int precision, int switch_t);
+bool tuned_switch(int matrix_class, int64_t N, int precision, int* switch_t);
 Geo make_geo(bool fourier, int N);
 int transform_partials(int vk, const Geo& g);   // partials written by a transform
 

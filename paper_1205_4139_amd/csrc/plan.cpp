@@ -258,15 +258,82 @@ static int plan_enqueue_prefix(fcmp_plan& P, const fcmp_options& opt, hipStream_
   return FCMP_OK;
 }
 
+// One fast correlation (eq. (kernelsumOMP)) with t-1 taps and the fused
+// identification; returns the number of partials through npart.
+int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
+  ProfScope ps(FCMP_PHASE_FAST, st);
+  FParams fp{};
+  fp.N = (int)P.shape.N; fp.logN = P.g.logN; fp.fourier = P.g.fourier; fp.c_kind = P.pk;
+  fp.h0 = P.h0; fp.c = P.cp; fp.lam = P.lam; fp.x = P.x; fp.ntaps = t - 1;
+  fp.h = nullptr; fp.partial = P.partial; fp.excl = P.excl; fp.status = P.status;
+  fp.inst_h0 = P.sN; fp.inst_c = P.sN; fp.inst_lam = P.sK; fp.inst_x = P.sK;
+  fp.inst_h = 0; fp.inst_part = P.sP; fp.inst_excl = P.sE;
+  HIP_TRY(launch_fastcorr(fp, (int)P.n, npart, st));
+  return FCMP_OK;
+}
+
+// One conventional correlation at iteration t: the FP64 residual of the
+// t-1 selected columns (direct while M_i (t-1) <= ratio N log2 N, per
+// instance, else through a forward transform of S_Lambda^T x) and the
+// transform of the zero-filled residual with the fused identification.
+int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
+  const bool F = P.g.fourier;
+  const int n = (int)P.n;
+  const int N = (int)P.shape.N, M = (int)P.shape.M;
+  const Geo& g = P.g;
+  const EntDev en{P.ent_k, P.goff, M};
+  const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
+  const double thr = P.resid_ratio * (double)N * (double)g.logN;
+  int64_t m_lo = P.hM[0], m_hi = P.hM[0];
+  for (int32_t m : P.hM) { m_lo = std::min<int64_t>(m_lo, m); m_hi = std::max<int64_t>(m_hi, m); }
+  const double work_lo = (double)m_lo * (double)(t - 1);
+  const double work_hi = (double)m_hi * (double)(t - 1);
+  if (work_hi > thr) {
+    ProfScope ps(FCMP_PHASE_RESID, st);
+    XSrc src{IN_TAPS, P.wk, nullptr};
+    src.taps_lam = P.lam; src.taps_x = P.x; src.ntaps = t - 1;
+    src.inst_lam = P.sK; src.inst_x = P.sK;
+    XDst d;
+    d.scale = inv_sqrt_n;
+    d.resid = true;
+    d.ent2_k = P.ent2_k; d.goff2 = P.goff2; d.pos1 = P.pos1; d.nent2 = M;
+    d.yres = P.y_ent; d.yres_kind = P.wk; d.rout = P.r; d.r_kind = P.pk;
+    d.inst_ent2 = P.sM; d.inst_goff2 = P.g.same_out ? P.sG : P.sG2;
+    d.inst_yres = P.sM; d.inst_rout = P.sM;
+    if (work_lo <= thr) { d.rsel_M = P.Mv; d.rsel_ntaps = t - 1; d.rsel_thr = thr; }
+    HIP_TRY(run_transform(P.wk, -1, g, tw_for(P, P.wk), en, src, d, P.tmp, P.status, st, n,
+                          P.sN, P.sM, 0, 0, P.sG));
+  }
+  if (work_lo <= thr) {
+    ProfScope ps(FCMP_PHASE_RESID, st);
+    RParams rp{};
+    rp.N = N; rp.logN = g.logN; rp.twS = g.twS; rp.fourier = F; rp.M = M;
+    rp.ent_k = P.ent_k; rp.y = P.y_ent; rp.r = P.r; rp.r_kind = P.pk;
+    rp.lam = P.lam; rp.x = P.x; rp.ntaps = t - 1;
+    rp.tw_lo = P.tw64; rp.tw_hi = P.tw64 + ((size_t)1 << g.twS);
+    rp.status = P.status;
+    rp.inst_ent = P.sM; rp.inst_y = P.sM; rp.inst_r = P.sM; rp.inst_lam = P.sK;
+    rp.inst_x = P.sK;
+    if (work_hi > thr) { rp.Mv = P.Mv; rp.thr = thr; }
+    HIP_TRY(launch_residual(rp, n, st));
+  }
+  ProfScope ps(FCMP_PHASE_CORR, st);
+  XDst d;
+  d.partial = P.partial; d.excl = P.excl;
+  d.scale = inv_sqrt_n;
+  HIP_TRY(run_transform(P.pk, +1, g, tw_for(P, P.pk), en, XSrc{IN_SPARSE, P.pk, P.r}, d, P.tmp,
+                        P.status, st, n, P.sN, P.sM, P.sP, P.sE, P.sG));
+  *npart = transform_partials(P.pk, g);
+  return FCMP_OK;
+}
+
 int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
   int rc = plan_enqueue_prefix(P, opt, st);
   if (rc) return rc;
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
   const int n = (int)P.n;
-  const int N = (int)P.shape.N, M = (int)P.shape.M, K = (int)P.shape.K;
+  const int N = (int)P.shape.N, K = (int)P.shape.K;
   const Geo& g = P.g;
-  const EntDev en{P.ent_k, P.goff, M};
-  const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
   LParams lp{};
   lp.N = N; lp.fourier = F;
   lp.partial = P.partial; lp.npart = transform_partials(P.wk, g);
@@ -277,72 +344,21 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
   lp.wbuf = P.wbuf; lp.inst_wbuf = P.sK;
   lp.vpart = P.vpart; lp.inst_vpart = 16 * P.sK; lp.vpart_stride = P.sK;
   lp.Kv = P.Kv;
-  // residual per instance: direct while M_i (t-1) <= thr, then through a
-  // forward transform of S_Lambda^T x
-  const double thr = P.resid_ratio * (double)N * (double)g.logN;
-  int64_t m_lo = P.hM[0], m_hi = P.hM[0];
-  for (int32_t m : P.hM) { m_lo = std::min<int64_t>(m_lo, m); m_hi = std::max<int64_t>(m_hi, m); }
   lp.t = 1;
   {
     ProfScope ps(FCMP_PHASE_LS, st);
     HIP_TRY(launch_ls_update(lp, n, st));
   }
-  const int switch_t =
-      opt.switch_t > 0 ? opt.switch_t : (F ? 2 + (5 * g.logN) / 6 : 1 + g.logN);
+  const int switch_t = opt.switch_t > 0
+                           ? opt.switch_t
+                           : default_switch_t(P.shape.matrix_class, N, P.opt.corr_precision);
   for (int t = 2; t <= K; ++t) {
     const bool fast = opt.corr_method == FCMP_CORR_FAST ||
                       (opt.corr_method == FCMP_CORR_ADAPTIVE && t <= switch_t);
-    int npart;
-    if (fast) {
-      ProfScope ps(FCMP_PHASE_FAST, st);
-      FParams fp{};
-      fp.N = N; fp.logN = g.logN; fp.fourier = F; fp.c_kind = P.pk;
-      fp.h0 = P.h0; fp.c = P.cp; fp.lam = P.lam; fp.x = P.x; fp.ntaps = t - 1;
-      fp.h = nullptr; fp.partial = P.partial; fp.excl = P.excl; fp.status = P.status;
-      fp.inst_h0 = P.sN; fp.inst_c = P.sN; fp.inst_lam = P.sK; fp.inst_x = P.sK;
-      fp.inst_h = 0; fp.inst_part = P.sP; fp.inst_excl = P.sE;
-      HIP_TRY(launch_fastcorr(fp, n, &npart, st));
-    } else {
-      const double work_lo = (double)m_lo * (double)(t - 1);
-      const double work_hi = (double)m_hi * (double)(t - 1);
-      if (work_hi > thr) {
-        // residual through one FP64 forward transform of S_Lambda^T x
-        ProfScope ps(FCMP_PHASE_RESID, st);
-        XSrc src{IN_TAPS, P.wk, nullptr};
-        src.taps_lam = P.lam; src.taps_x = P.x; src.ntaps = t - 1;
-        src.inst_lam = P.sK; src.inst_x = P.sK;
-        XDst d;
-        d.scale = inv_sqrt_n;
-        d.resid = true;
-        d.ent2_k = P.ent2_k; d.goff2 = P.goff2; d.pos1 = P.pos1; d.nent2 = M;
-        d.yres = P.y_ent; d.yres_kind = P.wk; d.rout = P.r; d.r_kind = P.pk;
-        d.inst_ent2 = P.sM; d.inst_goff2 = P.g.same_out ? P.sG : P.sG2;
-        d.inst_yres = P.sM; d.inst_rout = P.sM;
-        if (work_lo <= thr) { d.rsel_M = P.Mv; d.rsel_ntaps = t - 1; d.rsel_thr = thr; }
-        HIP_TRY(run_transform(P.wk, -1, g, tw_for(P, P.wk), en, src, d, P.tmp, P.status, st, n,
-                              P.sN, P.sM, 0, 0, P.sG));
-      }
-      if (work_lo <= thr) {
-        ProfScope ps(FCMP_PHASE_RESID, st);
-        RParams rp{};
-        rp.N = N; rp.logN = g.logN; rp.twS = g.twS; rp.fourier = F; rp.M = M;
-        rp.ent_k = P.ent_k; rp.y = P.y_ent; rp.r = P.r; rp.r_kind = P.pk;
-        rp.lam = P.lam; rp.x = P.x; rp.ntaps = t - 1;
-        rp.tw_lo = P.tw64; rp.tw_hi = P.tw64 + ((size_t)1 << g.twS);
-        rp.status = P.status;
-        rp.inst_ent = P.sM; rp.inst_y = P.sM; rp.inst_r = P.sM; rp.inst_lam = P.sK;
-        rp.inst_x = P.sK;
-        if (work_hi > thr) { rp.Mv = P.Mv; rp.thr = thr; }
-        HIP_TRY(launch_residual(rp, n, st));
-      }
-      ProfScope ps(FCMP_PHASE_CORR, st);
-      XDst d;
-      d.partial = P.partial; d.excl = P.excl;
-      d.scale = inv_sqrt_n;
-      HIP_TRY(run_transform(P.pk, +1, g, tw_for(P, P.pk), en, XSrc{IN_SPARSE, P.pk, P.r}, d,
-                            P.tmp, P.status, st, n, P.sN, P.sM, P.sP, P.sE, P.sG));
-      npart = transform_partials(P.pk, g);
-    }
+    int npart = 0;
+    if (fast) rc = plan_fast_corr(P, t, &npart, st);
+    else rc = plan_conv_corr(P, t, &npart, st);
+    if (rc) return rc;
     lp.t = t;
     lp.npart = npart;
     ProfScope ps(FCMP_PHASE_LS, st);

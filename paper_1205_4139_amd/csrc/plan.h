@@ -74,6 +74,11 @@ int plan_kernel_vector(fcmp_plan& P, hipStream_t st);
 // OMP device work of one solve (no host synchronisation, so it can be
 // captured in a graph); the pointer array dptrs must already be uploaded.
 int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st);
+// One correlation of iteration t (t-1 selected columns) with the fused
+// identification, by the fast method or the conventional one (residual and
+// transform); npart receives the number of identification partials.
+int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st);
+int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st);
 // Fills stats from host copies of the status records; FCMP_E_NUMERIC when any
 // instance broke down.
 int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats);

@@ -149,3 +149,22 @@ def test_server_create_rejects_missing_pool(fc):
     h = ctypes.c_void_p(0)
     assert fc.lib.fcmp_server_create(ctypes.byref(h), None, 1 << 20, None) == -1
     assert b"pool" in fc.lib.fcmp_last_error()
+
+
+def test_adaptive_switch_model_and_cache(fc, tmp_path):
+    """Untuned switch iterations follow Table I's flop model; a cache file
+    loads tuned entries (a size no other test uses)."""
+    t, tuned = fc.adaptive_switch("F", 65536, "fp32")
+    assert not tuned and t == 2 + (5 * 16) // 6
+    t, tuned = fc.adaptive_switch("H", 1 << 20, "fp64")
+    assert not tuned and t == 1 + 20
+    path = tmp_path / "switch.txt"
+    path.write_text("1 2097152 1 9\n0 2097152 0 23\nbogus line\n")
+    fc.autotune_load(path)
+    assert fc.adaptive_switch("F", 1 << 21, "fp32") == (9, True)
+    assert fc.adaptive_switch("H", 1 << 21, "fp64") == (23, True)
+    (tmp_path / "empty.txt").write_text("")
+    with pytest.raises(fc.FcmpError, match="no valid entries"):
+        fc.autotune_load(tmp_path / "empty.txt")
+    with pytest.raises(fc.FcmpError, match="power of two"):
+        fc.adaptive_switch("F", 1000, "fp32")

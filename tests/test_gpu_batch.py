@@ -199,3 +199,24 @@ def test_lockstep_plan_with_mixed_m_and_k(fc, precision, monkeypatch):
         if certify.certified(ref, precision):
             assert list(to_np(sups[k])) == list(ref.support)
             assert np.linalg.norm(to_np(xs[k]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+def test_autotuned_adaptive_switch(fc, tmp_path):
+    """The autotuner records a measured switch iteration; adaptive solves with
+    switch_t = 0 then use it, bit for bit as when it is passed explicitly, and
+    a cache file written by one call short-cuts the next."""
+    cache = str(tmp_path / "tune.txt")
+    t = fc.autotune("F", 16384, 4096, "fp32", batch=4, cache_path=cache)
+    assert 1 <= t <= 8 * (2 + (5 * 14) // 6) + 8
+    assert fc.adaptive_switch("F", 16384, "fp32") == (t, True)
+    assert open(cache).read().split() == ["1", "16384", "1", str(t)]
+    assert fc.autotune("F", 16384, 4096, "fp32", batch=4, cache_path=cache) == t
+    data = _insts("F", 16384, 4096, 40, "cgauss", 30.0, 2, 8800)
+    plan = fc.Plan("F", 16384, 4096, 40, [d[0].omega for d in data], precision="fp32",
+                   method="adaptive")
+    import torch
+    ys = torch.stack([to_dev(d[1]) for d in data])
+    s1, x1, _ = plan.solve(ys, method="adaptive")
+    s1, x1 = to_np(s1).copy(), to_np(x1).copy()
+    s2, x2, _ = plan.solve(ys, method="adaptive", switch_t=t)
+    assert np.array_equal(s1, to_np(s2)) and np.array_equal(x1, to_np(x2))

@@ -224,6 +224,65 @@ def serve_leg(fc, device, count: int, rate_hz: float):
     }
 
 
+def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
+    """HBM bytes per conventional-correlation launch pair (complex64 pass 1 +
+    pass 2 at the workload's grid) from two rocprofv3 --pmc runs of this
+    script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by
+    what the same counter reads for the plain copy of --copy-probe-mib MiB.
+    Written to profiles/pmc_traffic.json with the kernel-source hash."""
+    import csv
+    import statistics
+    from collections import Counter, defaultdict
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"].startswith(counter)]
+        return rows
+
+    out = {}
+    factors = {}
+    per = {}
+    for counter, path, moved in (("FETCH_SIZE", fetch_csv, "read"), ("WRITE_SIZE", write_csv, "write")):
+        rows = load(path, counter)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]
+                  or "copy" in r["Kernel_Name"].lower()]
+        if not copies:
+            raise SystemExit(f"no copy dispatch in {path}")
+        probe = max(copies) * 1024.0            # bytes the counter saw for the probe
+        known = float(os.environ.get("PMC_PROBE_BYTES", 256 << 20))
+        factors[counter] = known / probe
+        by = defaultdict(list)
+        grids = Counter()
+        for r in rows:
+            name = r["Kernel_Name"]
+            if "xform_kernel<HIP_vector_type<float, 2u>, true, 1>" in name:
+                key = "pass1"
+            elif "xform_kernel<HIP_vector_type<float, 2u>, true, 2>" in name:
+                key = "pass2"
+            else:
+                continue
+            by[(key, int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+            grids[(key, int(r["Grid_Size"]))] += 1
+        for key in ("pass1", "pass2"):
+            g = max((k for k in grids if k[0] == key), key=lambda k: grids[k])
+            per[(counter, key)] = statistics.median(by[g]) * 1024.0 * factors[counter]
+    total = sum(per.values())
+    out["corr_c64_n65536"] = {
+        "kernel_hash": kernel_hash(),
+        "bytes_per_launch": round(total),
+        "fetch_factor": round(factors["FETCH_SIZE"], 4),
+        "write_factor": round(factors["WRITE_SIZE"], 4),
+        "pass1_read": round(per[("FETCH_SIZE", "pass1")]),
+        "pass1_write": round(per[("WRITE_SIZE", "pass1")]),
+        "pass2_read": round(per[("FETCH_SIZE", "pass2")]),
+        "pass2_write": round(per[("WRITE_SIZE", "pass2")]),
+    }
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,7 +299,12 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/pmc_traffic.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc)))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(instances would shard across GPUs with no exchange; see DESIGN.md)",
@@ -308,7 +372,7 @@ def main():
 
     # ---- adaptive with the switch iteration measured by the autotuner
     model_t, _ = fc.adaptive_switch("F", N, "fp32")
-    tuned_t = fc.autotune("F", N, M, "fp32", batch=16, device=dev)
+    tuned_t = fc.autotune("F", N, M, "fp32", batch=B, device=dev)
     if args.steps > 0:
         t = time_steps(lambda: plan.solve(ys, method="adaptive"), args.steps, 1)
         methods["adaptive_tuned"] = {"ms_per_step": round(t * 1e3, 3),

@@ -171,14 +171,16 @@ int wg_build(WgBatch& B, const fcmp_problem* probs, hipStream_t st) {
   {
     Geo gm = make_geo(true, 1 << WG_LOGT);
     gm.hmax = 0;
-    build_tables(gm, nullptr, 0, t);
+    HostTables tf;
+    build_tables(gm, nullptr, 0, tf);
     std::vector<double2> s64;
     std::vector<float2> s32;
     build_stage_table(B.hmax, s64, s32);
-    t.tw64.insert(t.tw64.end(), s64.begin(), s64.end());
-    t.tw32.insert(t.tw32.end(), s32.begin(), s32.end());
-    HIP_TRY(hipMemcpyAsync(B.tw64, t.tw64.data(), t.tw64.size() * 16, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemcpyAsync(B.tw32, t.tw32.data(), t.tw32.size() * 8, hipMemcpyHostToDevice, st));
+    tf.tw64.insert(tf.tw64.end(), s64.begin(), s64.end());
+    tf.tw32.insert(tf.tw32.end(), s32.begin(), s32.end());
+    HIP_TRY(hipMemcpyAsync(B.tw64, tf.tw64.data(), tf.tw64.size() * 16, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(B.tw32, tf.tw32.data(), tf.tw32.size() * 8, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // tf is local
   }
   std::vector<double> cost(n);
   for (WgGroup& G : B.groups) {

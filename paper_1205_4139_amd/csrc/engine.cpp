@@ -159,6 +159,11 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
     t.pos1.clear();
   }
   // twiddles e^{+2 pi i q / N}: lo for q < 2^twS, hi for q * 2^twS, q < N >> twS
+  // (kept when this table set already holds them for the same geometry)
+  if (t.tw_N == g.N && t.tw_twS == g.twS && t.tw_hmax == g.hmax) return;
+  t.tw_N = g.N;
+  t.tw_twS = g.twS;
+  t.tw_hmax = g.hmax;
   const int nlo = 1 << g.twS, nhi = g.N >> g.twS;
   t.tw64.resize(nlo + nhi);
   t.tw32.resize(nlo + nhi);

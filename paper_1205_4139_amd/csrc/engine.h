@@ -58,6 +58,7 @@ struct HostTables {
   std::vector<int32_t> ent2_k, goff2, pos1; // rows grouped by pass-2 output workgroup
   std::vector<double2> tw64;                // lo (2^twS), hi (N >> twS), stage table; sign +
   std::vector<float2> tw32;
+  int tw_N = 0, tw_twS = -1, tw_hmax = -1;  // geometry the twiddles were built for
 };
 void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t);
 

@@ -52,24 +52,36 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   // addresses) before their LDS writes, so each thread waits for memory once
   // per batch rather than once per element.
   constexpr int XU = sizeof(V) >= 16 ? 4 : 8;
+  // inter-pass twiddles: the first two per thread are loaded now (clamped
+  // indices, so the loads are unconditional) and stored with the inputs
+  const V* glo = (const V*)p.tw_lo;
+  const V* ghi = (const V*)p.tw_hi;
+  const int ntw = nlo + nhi;
+  V tw0 = vzero(V()), tw1 = vzero(V());
   if (itw) {
-    const V* glo = (const V*)p.tw_lo;
-    const V* ghi = (const V*)p.tw_hi;
-    const int ntw = nlo + nhi;
-    for (int e0 = tid; e0 < ntw; e0 += nt * XU) {
-      V w[XU];
-#pragma unroll
-      for (int u = 0; u < XU; ++u) {
-        const int e = min(e0 + u * nt, ntw - 1);
-        w[u] = e < nlo ? glo[e] : ghi[e - nlo];
-      }
-#pragma unroll
-      for (int u = 0; u < XU; ++u) {
-        const int e = e0 + u * nt;
-        if (e < ntw) twlo[e] = w[u];   // twhi follows twlo contiguously
-      }
-    }
+    const int e0 = min(tid, ntw - 1), e1 = min(tid + nt, ntw - 1);
+    tw0 = e0 < nlo ? glo[e0] : ghi[e0 - nlo];
+    tw1 = e1 < nlo ? glo[e1] : ghi[e1 - nlo];
   }
+
+  // the exclusion words the identification needs: the first one per thread
+  // is loaded now, in flight with the input loads, and written to LDS with
+  // them (the transform's barriers order it before its use)
+  const uint32_t* excl = p.excl ? p.excl + (int64_t)inst * p.inst_excl : nullptr;
+  uint32_t* xw = (uint32_t*)(red + 16);
+  int64_t xbase = 0, xstride = 1;
+  int nxw = 0;
+  if (p.partial && excl && p.excl_mode == 1) {
+    const int64_t o0 = (int64_t)s0 * p.out_ss;
+    xbase = o0 >> 5;
+    nxw = (int)(((o0 + tile_n - 1) >> 5) - xbase + 1);
+  } else if (p.partial && excl && p.excl_mode == 2) {
+    xbase = s0 >> 5;
+    xstride = p.out_es >> 5;
+    nxw = L;
+  }
+  uint32_t xw0 = 0;
+  if (tid < nxw) xw0 = excl[xbase + (int64_t)tid * xstride];
 
   // ---- load
   if (p.in_mode == IN_DENSE) {
@@ -158,6 +170,13 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
       }
     }
   }
+  if (itw) {
+    twlo[min(tid, ntw - 1)] = tw0;   // twhi follows twlo contiguously
+    twlo[min(tid + nt, ntw - 1)] = tw1;
+    for (int e = tid + 2 * nt; e < ntw; e += nt) twlo[e] = e < nlo ? glo[e] : ghi[e - nlo];
+  }
+  if (tid < nxw) xw[tid] = xw0;
+  for (int e = tid + nt; e < nxw; e += nt) xw[e] = excl[xbase + (int64_t)e * xstride];
   __syncthreads();
 
   // ---- transform
@@ -211,22 +230,6 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   KT bkey = (KT)-1;
   int bidx = -1;
   const bool store = p.out_kind >= 0 || p.out2_kind >= 0;
-  const uint32_t* excl = p.excl ? p.excl + (int64_t)inst * p.inst_excl : nullptr;
-  // stage the exclusion bits this workgroup needs
-  uint32_t* xw = (uint32_t*)(red + 16);
-  int64_t xbase = 0;
-  if (p.partial && excl && p.excl_mode) {
-    if (p.excl_mode == 1) {
-      const int64_t o0 = (int64_t)s0 * p.out_ss;
-      xbase = o0 >> 5;
-      const int nw = (int)(((o0 + tile_n - 1) >> 5) - xbase + 1);
-      for (int e = tid; e < nw; e += nt) xw[e] = excl[xbase + e];
-    } else {
-      const int64_t wstride = p.out_es >> 5;
-      for (int e = tid; e < L; e += nt) xw[e] = excl[(s0 >> 5) + e * wstride];
-    }
-    __syncthreads();
-  }
   const int out_ss = (int)p.out_ss, out_es = (int)p.out_es;
   for (int e = tid; e < tile_n; e += nt) {
     int c, j, pos;

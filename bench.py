@@ -207,6 +207,7 @@ def serve_leg(fc, device, count: int, rate_hz: float):
     info = srv.info()
     srv.close()
     sub = np.array([r["times"][0] for r in res])
+    launch = np.array([r["times"][1] for r in res])
     done = np.array([r["times"][2] for r in res])
     lat = done - sub
     span = (done.max() - sub.min()) / 1e3
@@ -215,9 +216,11 @@ def serve_leg(fc, device, count: int, rate_hz: float):
         "workload": f"{count}-request Poisson stream at {rate_hz:.0f} req/s: F/H, N = 2^U{{12..18}}, "
                     "M ~ U{N/8..N/4}, K ~ U{16..M/16}, 30 dB, complex64/FP32 correlation",
         "offered_req_per_s": round(count / max(t_sub, 1e-9), 1),
-        "completed_req_per_s": round(count / span, 1),
+        "completed_req_per_s": round(float(count / span), 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                        "p99": round(float(np.percentile(lat, 99)), 2)},
+        "queue_ms": {"p50": round(float(np.percentile(launch - sub, 50)), 2),
+                     "p99": round(float(np.percentile(launch - sub, 99)), 2)},
         "waves": int(info["waves"]),
         "pool_peak_GiB": round(info["pool_peak"] / 2**30, 2),
         "support_recovery_rate": rec,
@@ -296,6 +299,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
+    ap.add_argument("--serve-sustained", type=int, default=200,
+                    help="requests of a second stream at --serve-sustained-rate (0: skip)")
+    ap.add_argument("--serve-sustained-rate", type=float, default=100.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -401,6 +407,10 @@ def main():
     if args.serve_requests > 0:
         serve = serve_leg(fc, dev, args.serve_requests, args.serve_rate)
         print(f"[bench] serve: {serve}", file=sys.stderr, flush=True)
+    serve_low = None
+    if args.serve_sustained > 0:
+        serve_low = serve_leg(fc, dev, args.serve_sustained, args.serve_sustained_rate)
+        print(f"[bench] serve (sustained rate): {serve_low}", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -428,6 +438,7 @@ def main():
         "phases": phases,
         "uneven_batch": batch,
         "serving": serve,
+        "serving_sustained": serve_low,
         "roofline": {
             "kernel": "conventional correlation (xform pass 1 + pass 2, complex64, B instances)",
             "bound": "hbm",

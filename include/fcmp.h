@@ -109,6 +109,13 @@ typedef struct {
 /* fcmp_batch_solve runs every problem as a lockstep plan, never in the
  * persistent one-workgroup-per-problem kernel. */
 #define FCMP_FLAG_NO_PERSISTENT 2u
+/* Hadamard plans with M < 2^15 store the kernel vector's integers N c
+ * (|N c(j)| <= M; Sec. III-B notes the few distinct values) as int16 and the
+ * fast correlation gathers those, half the bytes of FP32 and a quarter of
+ * FP64; c = (N c)/N is exact, so results are bit-identical to the
+ * floating-point gathers.  This flag makes a solve gather the floating-point
+ * copy instead. */
+#define FCMP_FLAG_FLOAT_KERNEL 4u
 
 typedef struct {
   int32_t iterations;        /* OMP: selections made; SP/CoSaMP: outer iterations */

@@ -378,6 +378,7 @@ def profile_read(reset=True) -> dict:
 
 
 FLAG_NO_PERSISTENT = 2
+FLAG_FLOAT_KERNEL = 4
 
 
 def batch_solve(problems, ys, algorithm="omp", method="conventional", precision="fp64",

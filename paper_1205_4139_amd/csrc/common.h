@@ -14,6 +14,8 @@ template <> struct VT<float>   { using S = float;  using Wide = double;  static 
 template <> struct VT<double>  { using S = double; using Wide = double;  static constexpr bool cplx = false; };
 template <> struct VT<float2>  { using S = float;  using Wide = double2; static constexpr bool cplx = true; };
 template <> struct VT<double2> { using S = double; using Wide = double2; static constexpr bool cplx = true; };
+// Hadamard kernel vector stored as the integers N c (F3 variant)
+template <> struct VT<int16_t> { using S = int16_t; using Wide = double; static constexpr bool cplx = false; };
 
 __host__ __device__ inline float  vzero(float)   { return 0.f; }
 __host__ __device__ inline double vzero(double)  { return 0.0; }

@@ -17,6 +17,7 @@ constexpr int F_TCH = 1024;   // taps staged in LDS per chunk
 template <class VC> __device__ __forceinline__ double cwiden(VC v);
 template <> __device__ __forceinline__ double cwiden<float>(float v) { return (double)v; }
 template <> __device__ __forceinline__ double cwiden<double>(double v) { return v; }
+template <> __device__ __forceinline__ double cwiden<int16_t>(int16_t v) { return (double)v; }
 template <class VC> __device__ __forceinline__ double2 cwiden2(VC v);
 template <> __device__ __forceinline__ double2 cwiden2<float2>(float2 v) {
   return make_double2((double)v.x, (double)v.y);
@@ -53,23 +54,37 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
       sx[e] = xg[base + e];
     }
     __syncthreads();
-    for (int tau = 0; tau < n; ++tau) {
-      const uint32_t l = (uint32_t)sl[tau];
-      const Wd xv = sx[tau];
-      VC cv[JPT];
+    // FTU taps per step: their gathers are all in flight before the first
+    // product (the products are still accumulated in tap order)
+    constexpr int FTU = JPT == 1 ? 8 : (JPT == 2 ? 4 : 2);
+    for (int tau0 = 0; tau0 < n; tau0 += FTU) {
+      VC cv[FTU][JPT];
 #pragma unroll
-      for (int u = 0; u < JPT; ++u) {
-        const uint32_t j = (uint32_t)(jb + u * F_THREADS) & mask;
-        cv[u] = c[perm_index(FOURIER, j, l, mask)];
+      for (int q = 0; q < FTU; ++q) {
+        const uint32_t l = (uint32_t)sl[min(tau0 + q, n - 1)];
+#pragma unroll
+        for (int u = 0; u < JPT; ++u) {
+          const uint32_t j = (uint32_t)(jb + u * F_THREADS) & mask;
+          cv[q][u] = c[perm_index(FOURIER, j, l, mask)];
+        }
       }
 #pragma unroll
-      for (int u = 0; u < JPT; ++u) {
-        if constexpr (FOURIER) {
-          const double2 cw = cwiden2<VC>(cv[u]);
-          acc[u].x -= xv.x * cw.x - xv.y * cw.y;
-          acc[u].y -= xv.x * cw.y + xv.y * cw.x;
-        } else {
-          acc[u] -= xv * cwiden<VC>(cv[u]);
+      for (int q = 0; q < FTU; ++q) {
+        if (tau0 + q < n) {   // uniform
+          const Wd xv = sx[tau0 + q];
+#pragma unroll
+          for (int u = 0; u < JPT; ++u) {
+            if constexpr (FOURIER) {
+              const double2 cw = cwiden2<VC>(cv[q][u]);
+              acc[u].x -= xv.x * cw.x - xv.y * cw.y;
+              acc[u].y -= xv.x * cw.y + xv.y * cw.x;
+            } else if constexpr (std::is_same<VC, int16_t>::value) {
+              // (N c) / N is exact, so this equals the floating-point kernel path
+              acc[u] -= xv * (cwiden<VC>(cv[q][u]) * p.cscale);
+            } else {
+              acc[u] -= xv * cwiden<VC>(cv[q][u]);
+            }
+          }
         }
       }
     }
@@ -122,6 +137,7 @@ static hipError_t launch_v(const FParams& p, int ninst, hipStream_t st) {
 
 hipError_t launch_fastcorr(const FParams& p, int ninst, int* groups_out, hipStream_t st) {
   if (groups_out) *groups_out = fastcorr_groups(p.N);
+  if (p.c_int16) return launch_v<int16_t>(p, ninst, st);
   switch (p.c_kind) {
     case V_F32: return launch_v<float>(p, ninst, st);
     case V_F64: return launch_v<double>(p, ninst, st);

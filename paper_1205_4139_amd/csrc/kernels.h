@@ -111,6 +111,8 @@ struct FParams {
   int N, logN;
   int fourier;
   int c_kind;              // VKind of the stored kernel vector
+  int c_int16;             // Hadamard: c holds the integers N c as int16 (c_kind ignored)
+  double cscale;           //   and c(j) = cscale * (N c)(j), cscale = 1/N (exact)
   const void* h0;          // FP64 (wide)
   const void* c;
   const int32_t* lam;
@@ -154,6 +156,10 @@ int ls_split_groups(int t);   // workgroups per instance used at iteration t
 
 // ------------------------------------------------------------------ utilities
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+// out[i] = round(mul * in[i]) as int16 for n values of ninst instances
+// (the Hadamard kernel vector's integers N c)
+hipError_t launch_to_int16(const double* in, int16_t* out, double mul, int64_t n, int64_t inst_in,
+                           int64_t inst_out, int ninst, hipStream_t st);
 hipError_t launch_gather_wide(int vk, const void* src, const int32_t* idx, void* dst,
                               int64_t n, int64_t inst_src, int64_t inst_idx, int64_t inst_dst,
                               int ninst, hipStream_t st);

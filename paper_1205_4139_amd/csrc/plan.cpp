@@ -95,6 +95,9 @@ void plan_layout(fcmp_plan& P, char* base) {
   }
   P.c64 = cv.take_bytes(n * P.sN * wb);
   P.cp = P.pk == P.wk ? P.c64 : cv.take_bytes(n * P.sN * pb);
+  // Hadamard: |N c(j)| <= M, so N c fits int16 when M < 2^15 (Sec. III-B:
+  // the kernel vector takes few distinct values)
+  P.ci16 = (!P.g.fourier && P.shape.M < (1 << 15)) ? cv.take<int16_t>(n * P.sN) : nullptr;
   P.y_ent = cv.take_bytes(n * P.sM * wb);
   P.r = cv.take_bytes(n * P.sM * pb);
   P.h0 = cv.take_bytes(n * P.sN * wb);
@@ -144,6 +147,9 @@ int plan_kernel_vector(fcmp_plan& P, hipStream_t st) {
   HIP_TRY(run_transform(P.wk, +1, P.g, tw_for(P, P.wk),
                         EntDev{P.ent_k, P.goff, (int)P.shape.M}, XSrc{IN_SPARSE_ONES, P.wk, nullptr},
                         d, P.tmp, nullptr, st, (int)P.n, P.sN, P.sM, 0, 0, P.sG));
+  if (P.ci16)
+    HIP_TRY(launch_to_int16((const double*)P.c64, P.ci16, (double)P.shape.N, P.shape.N, P.sN, P.sN,
+                            (int)P.n, st));
   return FCMP_OK;
 }
 
@@ -228,6 +234,7 @@ int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats) {
 // h_0 with the first identification: device work only.
 static int plan_enqueue_prefix(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
   int rc = FCMP_OK;
+  P.cur_flags = opt.flags;
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
   const int n = (int)P.n;
   const int N = (int)P.shape.N, M = (int)P.shape.M;
@@ -265,6 +272,11 @@ int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
   FParams fp{};
   fp.N = (int)P.shape.N; fp.logN = P.g.logN; fp.fourier = P.g.fourier; fp.c_kind = P.pk;
   fp.h0 = P.h0; fp.c = P.cp; fp.lam = P.lam; fp.x = P.x; fp.ntaps = t - 1;
+  if (P.ci16 && !(P.cur_flags & FCMP_FLAG_FLOAT_KERNEL)) {
+    fp.c = P.ci16;
+    fp.c_int16 = 1;
+    fp.cscale = 1.0 / (double)P.shape.N;
+  }
   fp.h = nullptr; fp.partial = P.partial; fp.excl = P.excl; fp.status = P.status;
   fp.inst_h0 = P.sN; fp.inst_c = P.sN; fp.inst_lam = P.sK; fp.inst_x = P.sK;
   fp.inst_h = 0; fp.inst_part = P.sP; fp.inst_excl = P.sE;

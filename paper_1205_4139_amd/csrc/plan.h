@@ -31,6 +31,8 @@ struct fcmp_plan {
   int32_t* pos1 = nullptr;
   void* c64 = nullptr;
   void* cp = nullptr;
+  int16_t* ci16 = nullptr;     // Hadamard, M < 2^15: the integers N c (fast gathers)
+  uint32_t cur_flags = 0;      // flags of the solve being enqueued
   void* y_ent = nullptr;
   void* r = nullptr;
   void* h0 = nullptr;

@@ -25,6 +25,23 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
     p[i] = v;
 }
 
+__global__ void to_int16_kernel(const double* in, int16_t* out, double mul, int64_t n,
+                                int64_t ii, int64_t io) {
+  const int inst = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[inst * io + i] = (int16_t)rint(mul * in[inst * ii + i]);
+}
+
+hipError_t launch_to_int16(const double* in, int16_t* out, double mul, int64_t n, int64_t inst_in,
+                           int64_t inst_out, int ninst, hipStream_t st) {
+  int64_t groups = (n + 255) / 256;
+  if (groups > 1024) groups = 1024;
+  hipLaunchKernelGGL(to_int16_kernel, dim3((unsigned)groups, ninst), dim3(256), 0, st, in, out, mul,
+                     n, inst_in, inst_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   int64_t groups = (n + 255) / 256;

@@ -220,3 +220,24 @@ def test_autotuned_adaptive_switch(fc, tmp_path):
     s1, x1 = to_np(s1).copy(), to_np(x1).copy()
     s2, x2, _ = plan.solve(ys, method="adaptive", switch_t=t)
     assert np.array_equal(s1, to_np(s2)) and np.array_equal(x1, to_np(x2))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("method", ["fast", "adaptive"])
+def test_hadamard_integer_kernel_bit_identical(fc, method, precision):
+    """Hadamard plans with M < 2^15 gather the kernel vector's integers N c as
+    int16; since (N c)/N is exact, the solve equals the floating-point gather
+    bit for bit (and the oracle on certified instances)."""
+    import torch
+    data = _insts("H", 4096, 1000, 37, "gauss", 40.0, 3, 8900)
+    plan = fc.Plan("H", 4096, 1000, 37, [d[0].omega for d in data], precision=precision,
+                   method=method)
+    ys = torch.stack([to_dev(d[1]) for d in data])
+    s1, x1, _ = plan.solve(ys, method=method)
+    s1, x1 = to_np(s1).copy(), to_np(x1).copy()
+    s2, x2, _ = plan.solve(ys, method=method, flags=fc.FLAG_FLOAT_KERNEL)
+    assert np.array_equal(s1, to_np(s2)) and np.array_equal(x1, to_np(x2))
+    for b, (inst, y) in enumerate(data):
+        ref = oracle.omp(oracle.make_operator("H", 4096, inst.omega), y, 37)
+        if certify.certified(ref, precision):
+            assert list(s1[b]) == list(ref.support)

@@ -357,6 +357,7 @@ def main():
     prof = fc.profile_read(reset=True)
     sup, x, _ = plan.solve(ys, method="conventional", stats=False)
     torch.cuda.synchronize()
+    sup_np = sup.cpu().numpy().copy()
     recovered = float(np.mean([set(sup[i].cpu().numpy()) == set(insts[i].support)
                                for i in range(B)]))
 
@@ -381,6 +382,20 @@ def main():
         t = time_steps(lambda: plan.solve(ys, method=meth), steps, 1 if meth != "fast" else 0)
         methods[meth] = {"ms_per_step": round(t * 1e3, 3), "solves_per_s": round(B / t, 3)}
         print(f"[bench] {meth}: {t*1e3:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # ---- the same conventional step replayed from one captured graph
+    yl = [ys[i] for i in range(B)]
+    gp = fc.BatchPlan([("F", N, M, K, i.omega) for i in insts], method="conventional",
+                      precision="fp32", flags=fc.FLAG_RECOMPUTE_KERNEL, device=dev)
+    t_graph = time_steps(lambda: gp.solve(yl), args.steps, 1)
+    gsup = [t.cpu().numpy() for t in gp.support]
+    same = all(np.array_equal(gsup[i], sup_np[i]) for i in range(B))
+    methods["conventional_graph"] = {"ms_per_step": round(t_graph * 1e3, 3),
+                                     "solves_per_s": round(B / t_graph, 3),
+                                     "supports_equal_eager": bool(same)}
+    print(f"[bench] conventional, graph replay: {t_graph*1e3:.2f} ms/step (same supports: {same})",
+          file=sys.stderr, flush=True)
+    gp.close()
 
     # ---- adaptive with the switch iteration measured by the autotuner
     model_t, _ = fc.adaptive_switch("F", N, "fp32")

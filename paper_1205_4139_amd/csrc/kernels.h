@@ -79,6 +79,10 @@ struct XParams {
 hipError_t launch_xform(int vk, bool fft, const XParams& p, int groups, int ninst,
                         hipStream_t st);
 size_t xform_lds_bytes(int vk, bool fft, const XParams& p);
+// First pass of an FP64 two-pass transform of a taps input evaluated
+// directly (a few taps per column); ok when the tile and tap count suit it.
+bool taps_pass1_ok(const XParams& a, int vk);
+hipError_t launch_taps_pass1(const XParams& a, int vk, int groups, int ninst, hipStream_t st);
 
 // ------------------------------------------------------------------ residual
 // r[e] = y[e] - sum_tau U(k_e, lam_tau) x_tau for the current support, in FP64,

@@ -96,3 +96,52 @@ def test_server_ticket_collected_once(fc):
     with pytest.raises(fc.FcmpError, match="unknown ticket"):
         srv.poll(t)
     srv.close()
+
+
+def test_server_rejects_invalid_requests_without_disturbing_others(fc):
+    """Invalid requests fail at submit (host validation); the valid ones
+    around them complete exactly as they do alone."""
+    insts, ys = _stream()
+    srv = fc.Server(1 << 30)
+    good = []
+    for k, (i, y) in enumerate(zip(insts[:6], ys[:6])):
+        good.append(srv.submit(i.cls, i.N, i.M, i.K, i.omega, y, precision="fp32"))
+        if k == 2:
+            with pytest.raises(fc.FcmpError, match="K must be"):
+                srv.submit(i.cls, i.N, i.M, i.M, i.omega, y, precision="fp32")
+            bad_om = np.array(i.omega[::-1])
+            with pytest.raises(fc.FcmpError, match="strictly increasing"):
+                srv.submit(i.cls, i.N, i.M, i.K, bad_om, y, precision="fp32")
+    srv.drain(120000)
+    got = [srv.poll(t) for t in good]
+    info = srv.info()
+    srv.close()
+    assert info["submitted"] == info["completed"] == 6
+    alone, _ = _serve(fc, insts[:6], ys[:6], n_streams=1)
+    for a, b in zip(got, alone):
+        assert np.array_equal(a["support"], b["support"])
+        assert np.array_equal(a["x"], b["x"])
+
+
+def test_server_queue_full_is_busy(fc):
+    """One request slot and two queue places: while a long solve holds the
+    slot, the fourth submission is refused with FCMP_E_BUSY."""
+    big = instancegen.draw_instance("F", 1 << 18, 1 << 15, 1500, "cgauss", 30.0, 5200)
+    small = instancegen.draw_instance("H", 8192, 1600, 80, "gauss", 30.0, 5201)
+    yb = oracle.problem.instance_measure(big, tier="transform")
+    ysm = oracle.problem.instance_measure(small, tier="transform")
+    srv = fc.Server(4 << 30, max_slots=1, max_pending=2, n_streams=2)
+    t1 = srv.submit(big.cls, big.N, big.M, big.K, big.omega, yb, precision="fp32")
+    import time
+    t0 = time.time()
+    while srv.info()["inflight"] < 1 and time.time() - t0 < 30:   # t1 holds the slot
+        time.sleep(0.001)
+    assert srv.info()["inflight"] == 1
+    t2 = srv.submit(small.cls, small.N, small.M, small.K, small.omega, ysm, precision="fp32")
+    t3 = srv.submit(small.cls, small.N, small.M, small.K, small.omega, ysm, precision="fp32")
+    with pytest.raises(fc.FcmpError) as e:
+        srv.submit(small.cls, small.N, small.M, small.K, small.omega, ysm, precision="fp32")
+    assert e.value.code == fc.E_BUSY
+    srv.drain(300000)
+    assert all(srv.poll(t) is not None for t in (t1, t2, t3))
+    srv.close()

@@ -173,7 +173,7 @@ int fcmp_kernel_vector_workspace(const fcmp_problem* prob, size_t* bytes) {
   int rc = validate_problem(prob, false);
   if (rc) return rc;
   if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
-  const Geo g = make_geo(prob->matrix_class == FCMP_FOURIER, (int)prob->N);
+  const Geo g = make_geo(prob->matrix_class == FCMP_FOURIER, (int)prob->N, plan_tile(1));
   Carver cv;
   Common c;
   carve_kv(cv, g, (int)prob->M, c);
@@ -192,7 +192,7 @@ int fcmp_kernel_vector(const fcmp_problem* prob, int32_t precision, void* c64_de
   fcmp_kernel_vector_workspace(prob, &need);
   if (ws_bytes < need) return set_error(FCMP_E_WORKSPACE, "workspace too small");
   const bool F = prob->matrix_class == FCMP_FOURIER;
-  const Geo g = make_geo(F, (int)prob->N);
+  const Geo g = make_geo(F, (int)prob->N, plan_tile(1));
   Carver cv;
   cv.base = (char*)ws_dev;
   Common c;
@@ -217,7 +217,7 @@ int fcmp_correlate_workspace(const fcmp_problem* prob, int32_t precision, size_t
     return set_error(FCMP_E_INVALID, "unknown precision");
   if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
   const bool F = prob->matrix_class == FCMP_FOURIER;
-  const Geo g = make_geo(F, (int)prob->N);
+  const Geo g = make_geo(F, (int)prob->N, plan_tile(1));
   Carver cv;
   Common c;
   carve_common(cv, g, (int)prob->M, c);
@@ -235,7 +235,7 @@ int fcmp_correlate(const fcmp_problem* prob, int32_t precision, const void* r_de
   if (!r_dev || !ws_dev) return set_error(FCMP_E_INVALID, "NULL device pointer");
   if (ws_bytes < need) return set_error(FCMP_E_WORKSPACE, "workspace too small");
   const bool F = prob->matrix_class == FCMP_FOURIER;
-  const Geo g = make_geo(F, (int)prob->N);
+  const Geo g = make_geo(F, (int)prob->N, plan_tile(1));
   const int pk = prec_kind(F, precision);
   Carver cv;
   cv.base = (char*)ws_dev;
@@ -306,7 +306,7 @@ int fcmp_measure_workspace(const fcmp_problem* prob, size_t* bytes) {
   if (rc) return rc;
   if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
   const bool F = prob->matrix_class == FCMP_FOURIER;
-  const Geo g = make_geo(F, (int)prob->N);
+  const Geo g = make_geo(F, (int)prob->N, plan_tile(1));
   Carver cv;
   Common c;
   carve_common(cv, g, (int)prob->M, c);
@@ -326,7 +326,7 @@ int fcmp_measure(const fcmp_problem* prob, const void* x_dev, const void* noise_
   if (ws_bytes < need) return set_error(FCMP_E_WORKSPACE, "workspace too small");
   if (noise_dev && !std::isfinite(snr_db)) return set_error(FCMP_E_INVALID, "snr_db not finite");
   const bool F = prob->matrix_class == FCMP_FOURIER;
-  const Geo g = make_geo(F, (int)prob->N);
+  const Geo g = make_geo(F, (int)prob->N, plan_tile(1));
   const int wk = wide_kind(F);
   Carver cv;
   cv.base = (char*)ws_dev;

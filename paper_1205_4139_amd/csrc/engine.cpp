@@ -56,7 +56,15 @@ int default_switch_t(int matrix_class, int64_t N, int precision) {
   return model_switch_t(matrix_class, N);
 }
 
-Geo make_geo(bool fourier, int N) {
+int plan_tile(int64_t n) {
+  if (tune().tile_fixed) return tune().tile;
+  if (n <= 1) return 256;
+  if (n <= 8) return 512;
+  if (n <= 32) return 1024;
+  return tune().tile;
+}
+
+Geo make_geo(bool fourier, int N, int tile_req) {
   Geo g;
   g.N = N;
   g.fourier = fourier;
@@ -64,7 +72,7 @@ Geo make_geo(bool fourier, int N) {
   g.twS = g.logN / 2;
   g.n2 = g.logN / 2;
   g.n1 = g.logN - g.n2;
-  const int tile = tune().tile;
+  const int tile = tile_req > 0 ? tile_req : tune().tile;
   g.B1 = std::min(1 << g.n1, std::max(1, tile >> g.n2));
   g.B2 = std::min(1 << g.n2, std::max(1, tile >> g.n1));
   g.grouped = !single_ok(fourier ? V_C128 : V_F64, N);
@@ -187,7 +195,10 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
 const Tune& tune() {
   static const Tune t = [] {
     Tune v;
-    if (const char* e = std::getenv("FCMP_TILE")) v.tile = std::max(256, std::min(8192, std::atoi(e)));
+    if (const char* e = std::getenv("FCMP_TILE")) {
+      v.tile = std::max(256, std::min(8192, std::atoi(e)));
+      v.tile_fixed = true;
+    }
     if (const char* e = std::getenv("FCMP_THREADS")) v.threads = std::max(64, std::min(256, std::atoi(e)));
     return v;
   }();

@@ -38,6 +38,7 @@ void build_stage_table(int hmax, std::vector<double2>& t64, std::vector<float2>&
 struct Tune {
   int tile = 2048;
   int threads = 256;
+  bool tile_fixed = false;   // FCMP_TILE given: use it for every plan
 };
 const Tune& tune();
 
@@ -50,7 +51,14 @@ int default_switch_t(int matrix_class, int64_t N, int precision);
 int model_switch_t(int matrix_class, int64_t N);
 void set_tuned_switch(int matrix_class, int64_t N, int precision, int switch_t);
 bool tuned_switch(int matrix_class, int64_t N, int precision, int* switch_t);
-Geo make_geo(bool fourier, int N);
+// tile: values per workgroup tile of a two-pass transform (0: the tuned
+// default).  The tile changes only how work is split over workgroups, never a
+// result: every element's arithmetic and the identification's total order are
+// the same for any tile.
+Geo make_geo(bool fourier, int N, int tile = 0);
+// Tile for a lockstep plan of n instances: few instances need small tiles to
+// spread one transform over enough workgroups; many fill the chip anyway.
+int plan_tile(int64_t n);
 int transform_partials(int vk, const Geo& g);   // partials written by a transform
 
 struct HostTables {

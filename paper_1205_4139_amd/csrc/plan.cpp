@@ -48,7 +48,7 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
   P.shape.omega = nullptr;
   P.opt = *opt;
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
-  P.g = make_geo(F, (int)P.shape.N);
+  P.g = make_geo(F, (int)P.shape.N, plan_tile(n));
   P.wk = F ? V_C128 : V_F64;
   P.pk = opt->corr_precision == FCMP_FP32 ? (F ? V_C64 : V_F32) : P.wk;
   const int64_t N = P.shape.N, M = P.shape.M, K = P.shape.K;

@@ -391,9 +391,9 @@ __global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int G) {
 int ls_split_groups(int t) {
   const int n = t - 1;
   if (n < 64) return 1;
-  int G = n / 48;
+  int G = n / 24;
   if (G < 2) G = 2;
-  if (G > 16) G = 16;
+  if (G > LS_MAX_GROUPS) G = LS_MAX_GROUPS;
   return G;
 }
 

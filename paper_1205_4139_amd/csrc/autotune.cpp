@@ -116,13 +116,16 @@ int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_preci
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventCreate(&e2));
   int npart = 0;
+  std::vector<int32_t> hord, hbst;
   // warm up both paths
-  if ((rc = plan_fast_corr(P, 2, &npart, st)) || (rc = plan_conv_corr(P, 2, &npart, st))) {
+  if ((rc = plan_set_tap_order(P, lam.data(), 1, st, hord, hbst)) ||
+      (rc = plan_fast_corr(P, 2, &npart, st)) || (rc = plan_conv_corr(P, 2, &npart, st))) {
     hipEventDestroy(e0); hipEventDestroy(e1); hipEventDestroy(e2);
     return rc;
   }
   int best = 1;
   for (int t = 2; t <= P.shape.K; t += std::max(1, (t - 1) / 4)) {
+    if ((rc = plan_set_tap_order(P, lam.data(), t - 1, st, hord, hbst))) break;
     (void)hipEventRecord(e0, st);
     for (int r = 0; r < kReps && !rc; ++r) rc = plan_fast_corr(P, t, &npart, st);
     (void)hipEventRecord(e1, st);

@@ -205,7 +205,7 @@ const Tune& tune() {
   return t;
 }
 
-static int pick_threads(int tile_n) {
+int pick_threads(int tile_n) {
   int t = tile_n / 8;
   if (t < 64) t = 64;
   if (t > tune().threads) t = tune().threads;
@@ -282,10 +282,12 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   a.resid = 0;
   a.nthreads = pick_threads(a.L * a.B);
   a.role = 1;
-  hipError_t e = (in.mode == IN_TAPS && taps_pass1_ok(a, vk))
-                     ? launch_taps_pass1(a, vk, N1 / g.B1, ninst, st)
-                     : launch_xform(vk, fft, a, N1 / g.B1, ninst, st);
-  if (e != hipSuccess) return e;
+  if (!in.pass2_only) {
+    hipError_t e = (in.mode == IN_TAPS && taps_pass1_ok(a, vk))
+                       ? launch_taps_pass1(a, vk, N1 / g.B1, ninst, st)
+                       : launch_xform(vk, fft, a, N1 / g.B1, ninst, st);
+    if (e != hipSuccess) return e;
+  }
   // pass 2: N2 sequences (rows j2) of length N1 over k1
   XParams b = p;
   b.L = N1; b.logL = g.n1; b.B = g.B2;

@@ -60,6 +60,7 @@ Geo make_geo(bool fourier, int N, int tile = 0);
 // spread one transform over enough workgroups; many fill the chip anyway.
 int plan_tile(int64_t n);
 int transform_partials(int vk, const Geo& g);   // partials written by a transform
+int pick_threads(int tile_n);                    // threads of a transform workgroup
 
 struct HostTables {
   std::vector<int32_t> ent_k, perm, goff;   // entry order (grouped or Omega order)
@@ -74,6 +75,8 @@ struct TwDev { const void* lo; const void* hi; const void* st; };
 struct EntDev { const int32_t* ent_k; const int32_t* goff; int M; };
 struct XSrc {
   int mode; int kind; const void* ptr;
+  // two-pass transforms only: the first pass's output is already in tmp
+  bool pass2_only = false;
   // IN_TAPS
   const int32_t* taps_lam = nullptr; const void* taps_x = nullptr; int ntaps = 0;
   int64_t inst_lam = 0, inst_x = 0;

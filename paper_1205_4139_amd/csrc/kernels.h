@@ -84,6 +84,31 @@ size_t xform_lds_bytes(int vk, bool fft, const XParams& p);
 bool taps_pass1_ok(const XParams& a, int vk);
 hipError_t launch_taps_pass1(const XParams& a, int vk, int groups, int ninst, hipStream_t st);
 
+// ------------------------------------------------------------------ fused residual
+// The residual r = y - S_Omega U S_Lambda^T x at the rows of one first-pass
+// correlation workgroup, computed from the taps in FP64, followed by that
+// workgroup's correlation first pass (same geometry and output as pass 1 of
+// a two-pass transform).  Taps are read in bucket order: ord lists the tap
+// indices sorted by (bucket, index), taps of bucket l at [bstart[l],
+// bstart[l+1]); bucket = lam mod N2 (Fourier) or lam >> log2 N1 (Hadamard).
+struct RCParams {
+  int N, logN, twS;
+  int L, logL, B, logN1;   // L = N2 and B columns (k mod N1) per workgroup
+  const int32_t* lam; const void* x; const int32_t* ord; const int32_t* bstart; int ntaps;
+  int64_t inst_lam, inst_x, inst_ord, inst_bstart;
+  const int32_t* ent_k; const int32_t* goff;   // rows of Omega, grouped per workgroup
+  const void* y;           // FP64 (wide) in entry order
+  int64_t inst_ent, inst_goff, inst_y;
+  double rscale;           // N^{-1/2}
+  const void* twr_lo; const void* twr_hi; const void* twr_st;   // FP64 twiddles, sign +
+  const void* twc_lo; const void* twc_hi; const void* twc_st;   // correlation precision, sign +
+  void* out; int64_t inst_out;   // pass-1 output: out[(s0 + c) + N1 j]
+  const Status* status;
+};
+bool rcorr_ok(int pk, bool fft, const RCParams& p, int nthreads);
+hipError_t launch_rcorr(int pk, bool fft, const RCParams& p, int groups, int ninst, int nthreads,
+                        hipStream_t st);
+
 // ------------------------------------------------------------------ residual
 // r[e] = y[e] - sum_tau U(k_e, lam_tau) x_tau for the current support, in FP64,
 // stored in the correlation precision (Algorithm 1.1, step 7).
@@ -154,6 +179,11 @@ struct LParams {
   int64_t vpart_stride;
   const int32_t* Kv;       // nullable: per-instance K; an instance whose K
                            // selections are made is marked done at t = K + 1
+  // nullable: bucket order of the taps for the fused residual, two buffers
+  // per instance (parity of the tap count); bucket = (lam >> bshift) & (nbuck-1)
+  int32_t* ord; int32_t* bstart;
+  int64_t inst_ord, inst_bstart, ord_half, bstart_half;
+  int nbuck, bshift;
 };
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st);
 int ls_split_groups(int t);   // workgroups per instance used at iteration t

@@ -97,6 +97,26 @@ __device__ __forceinline__ void ls_rows_wh(const Wd* W, const Wd* w, int i_first
   }
 }
 
+// Bucket order of the taps for the fused residual: with taps 0..n-1 in
+// buffer n & 1 (tap indices sorted by (bucket, index) and the bucket starts),
+// writes taps 0..n, the new one being tap n of column j, to buffer (n+1) & 1.
+// The new tap has the largest index, so it goes to the end of its bucket.
+__device__ __forceinline__ void tap_order_insert(const LParams& p, int inst, int n, uint32_t j) {
+  const int NB = p.nbuck;
+  int32_t* ob = p.ord + (int64_t)inst * p.inst_ord;
+  int32_t* bb = p.bstart + (int64_t)inst * p.inst_bstart;
+  const int32_t* oold = ob + (n & 1) * p.ord_half;
+  int32_t* onew = ob + ((n + 1) & 1) * p.ord_half;
+  const int32_t* bold = bb + (n & 1) * p.bstart_half;
+  int32_t* bnew = bb + ((n + 1) & 1) * p.bstart_half;
+  const int key = (int)((j >> p.bshift) & (uint32_t)(NB - 1));
+  const int pos = n > 0 ? bold[key + 1] : 0;
+  for (int i = threadIdx.x; i <= n; i += blockDim.x)
+    onew[i] = i < pos ? oold[i] : (i == pos ? n : oold[i - 1]);
+  for (int b = threadIdx.x; b <= NB; b += blockDim.x)
+    bnew[b] = (n > 0 ? bold[b] : 0) + (b > key ? 1 : 0);
+}
+
 template <bool FOURIER>
 __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
@@ -222,6 +242,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
     st->iterations = p.t;
     st->last_key = best.key;
   }
+  if (p.ord) tap_order_insert(p, inst, n, j);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,6 +407,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int G) {
     st->znorm2 += vmag2(zt);
     st->iterations = p.t;
   }
+  if (cb == 0 && p.ord) tap_order_insert(p, inst, n, j);
 }
 
 int ls_split_groups(int t) {

@@ -17,6 +17,15 @@ namespace fcmp {
 
 static int64_t pad64(int64_t v) { return (v + 63) & ~int64_t(63); }
 
+// Geometry of the fused residual + first-pass launch: the correlation's
+// first pass (B1 columns of length N2 per workgroup).
+RCParams rcorr_geometry(const fcmp_plan& P) {
+  RCParams q{};
+  q.N = P.g.N; q.logN = P.g.logN; q.twS = P.g.twS;
+  q.L = 1 << P.g.n2; q.logL = P.g.n2; q.B = P.g.B1; q.logN1 = P.g.n1;
+  return q;
+}
+
 int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt) {
   if (n < 1) return set_error(FCMP_E_INVALID, "n must be >= 1");
   if (!probs) return set_error(FCMP_E_INVALID, "problems is NULL");
@@ -58,7 +67,15 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
   P.sW = pad64(K * (K + 1) / 2);
   P.sG = pad64(P.g.ngroups + 1);
   P.sG2 = pad64(P.g.ngroups2 + 1);
-  if (const char* e = std::getenv("FCMP_RESID_RATIO")) P.resid_ratio = std::atof(e);
+  const char* rr = std::getenv("FCMP_RESID_RATIO");
+  if (rr) P.resid_ratio = std::atof(rr);
+  // the residual fused into the correlation's first pass (OMP, two-pass
+  // correlation); FCMP_RESID_RATIO selects the separate residual kernels
+  if (opt->algorithm == FCMP_OMP && P.g.grouped && !single_ok(P.pk, (int)N) && !rr) {
+    RCParams q = rcorr_geometry(P);
+    P.fused = rcorr_ok(P.pk, F, q, pick_threads(q.B * q.L));
+  }
+  P.sB = pad64(((int64_t)1 << P.g.n2) + 1);
   P.npart = std::max(std::max(transform_partials(P.wk, P.g), transform_partials(P.pk, P.g)),
                      fastcorr_groups((int)N));
   P.sP = pad64(P.npart);
@@ -104,6 +121,12 @@ void plan_layout(fcmp_plan& P, char* base) {
   P.tmp = cv.take_bytes(n * P.sN * wb);
   P.partial = cv.take<Sel>(n * P.sP);
   P.lam = cv.take<int32_t>(n * P.sK);
+  if (P.fused) {
+    P.ord = cv.take<int32_t>(n * 2 * P.sK);
+    P.bst = cv.take<int32_t>(n * 2 * P.sB);
+  } else {
+    P.ord = P.bst = nullptr;
+  }
   P.excl = cv.take<uint32_t>(n * P.sE);
   P.x = cv.take_bytes(n * P.sK * wb);
   P.z = cv.take_bytes(n * P.sK * wb);
@@ -265,6 +288,29 @@ static int plan_enqueue_prefix(fcmp_plan& P, const fcmp_options& opt, hipStream_
   return FCMP_OK;
 }
 
+int plan_set_tap_order(fcmp_plan& P, const int32_t* lam, int ntaps, hipStream_t st,
+                       std::vector<int32_t>& ord, std::vector<int32_t>& bst) {
+  if (!P.fused) return FCMP_OK;
+  const int NB = 1 << P.g.n2;
+  const int shift = P.g.fourier ? 0 : P.g.n1;
+  ord.assign((size_t)(P.n * P.sK), 0);
+  bst.assign((size_t)(P.n * P.sB), 0);
+  for (int64_t b = 0; b < P.n; ++b) {
+    const int32_t* l = lam + b * P.sK;
+    int32_t* bs = &bst[(size_t)(b * P.sB)];
+    for (int k = 0; k < ntaps; ++k) ++bs[((l[k] >> shift) & (NB - 1)) + 1];
+    for (int q = 0; q < NB; ++q) bs[q + 1] += bs[q];
+    std::vector<int32_t> fill(bs, bs + NB);
+    for (int k = 0; k < ntaps; ++k) ord[(size_t)(b * P.sK + fill[(l[k] >> shift) & (NB - 1)]++)] = k;
+  }
+  const int par = ntaps & 1;
+  HIP_TRY(hipMemcpy2DAsync(P.ord + par * P.sK, 2 * P.sK * 4, ord.data(), P.sK * 4, P.sK * 4, P.n,
+                           hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpy2DAsync(P.bst + par * P.sB, 2 * P.sB * 4, bst.data(), P.sB * 4, P.sB * 4, P.n,
+                           hipMemcpyHostToDevice, st));
+  return FCMP_OK;
+}
+
 // One fast correlation (eq. (kernelsumOMP)) with t-1 taps and the fused
 // identification; returns the number of partials through npart.
 int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
@@ -295,6 +341,33 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
   const Geo& g = P.g;
   const EntDev en{P.ent_k, P.goff, M};
   const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
+  if (P.fused) {
+    ProfScope ps(FCMP_PHASE_CORR, st);
+    const int ntaps = t - 1;
+    RCParams q = rcorr_geometry(P);
+    q.lam = P.lam; q.x = P.x; q.ntaps = ntaps;
+    q.ord = P.ord + (ntaps & 1) * P.sK;
+    q.bstart = P.bst + (ntaps & 1) * P.sB;
+    q.inst_lam = P.sK; q.inst_x = P.sK; q.inst_ord = 2 * P.sK; q.inst_bstart = 2 * P.sB;
+    q.ent_k = P.ent_k; q.goff = P.goff; q.y = P.y_ent;
+    q.inst_ent = P.sM; q.inst_goff = P.sG; q.inst_y = P.sM;
+    q.rscale = inv_sqrt_n;
+    const TwDev tr = tw_for(P, P.wk), tc = tw_for(P, P.pk);
+    q.twr_lo = tr.lo; q.twr_hi = tr.hi; q.twr_st = tr.st;
+    q.twc_lo = tc.lo; q.twc_hi = tc.hi; q.twc_st = tc.st;
+    q.out = P.tmp; q.inst_out = P.sN;
+    q.status = P.status;
+    HIP_TRY(launch_rcorr(P.pk, F, q, (1 << g.n1) / g.B1, n, pick_threads(q.B * q.L), st));
+    XDst d;
+    d.partial = P.partial; d.excl = P.excl;
+    d.scale = inv_sqrt_n;
+    XSrc src{IN_SPARSE, P.pk, nullptr};
+    src.pass2_only = true;
+    HIP_TRY(run_transform(P.pk, +1, g, tw_for(P, P.pk), en, src, d, P.tmp, P.status, st, n,
+                          P.sN, P.sM, P.sP, P.sE, P.sG));
+    *npart = transform_partials(P.pk, g);
+    return FCMP_OK;
+  }
   const double thr = P.resid_ratio * (double)N * (double)g.logN;
   int64_t m_lo = P.hM[0], m_hi = P.hM[0];
   for (int32_t m : P.hM) { m_lo = std::min<int64_t>(m_lo, m); m_hi = std::max<int64_t>(m_hi, m); }
@@ -356,6 +429,13 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
   lp.wbuf = P.wbuf; lp.inst_wbuf = P.sK;
   lp.vpart = P.vpart; lp.inst_vpart = LS_MAX_GROUPS * P.sK; lp.vpart_stride = P.sK;
   lp.Kv = P.Kv;
+  if (P.fused) {
+    lp.ord = P.ord; lp.bstart = P.bst;
+    lp.inst_ord = 2 * P.sK; lp.ord_half = P.sK;
+    lp.inst_bstart = 2 * P.sB; lp.bstart_half = P.sB;
+    lp.nbuck = 1 << g.n2;
+    lp.bshift = F ? 0 : g.n1;
+  }
   lp.t = 1;
   {
     ProfScope ps(FCMP_PHASE_LS, st);

@@ -18,6 +18,8 @@ struct fcmp_plan {
   // per-instance strides in elements
   int64_t sM = 0, sN = 0, sK = 0, sW = 0, sG = 0, sG2 = 0, sP = 0, sE = 0;
   double resid_ratio = 1.0;    // transform residual when M (t-1) > ratio * N log2 N
+  bool fused = false;          // residual fused into the correlation's first pass
+  int64_t sB = 0;              // bucket starts per buffer (N2 + 1, padded)
   int npart = 1;
   // shared
   double2* tw64 = nullptr;
@@ -39,6 +41,8 @@ struct fcmp_plan {
   void* tmp = nullptr;
   fcmp::Sel* partial = nullptr;
   int32_t* lam = nullptr;
+  int32_t* ord = nullptr;      // fused residual: taps in bucket order, two buffers
+  int32_t* bst = nullptr;      //   and the bucket starts, two buffers
   uint32_t* excl = nullptr;
   void* x = nullptr;
   void* z = nullptr;
@@ -81,6 +85,12 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st);
 // transform); npart receives the number of identification partials.
 int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st);
 int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st);
+// Fused-residual plans: uploads the bucket order of taps 0..ntaps-1 given on
+// the host (lam: n * sK values), for conventional correlations run outside a
+// solve; ord and bst are host staging kept alive by the caller.
+int plan_set_tap_order(fcmp_plan& P, const int32_t* lam, int ntaps, hipStream_t st,
+                       std::vector<int32_t>& ord, std::vector<int32_t>& bst);
+RCParams rcorr_geometry(const fcmp_plan& P);
 // Fills stats from host copies of the status records; FCMP_E_NUMERIC when any
 // instance broke down.
 int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats);

@@ -77,13 +77,18 @@ LONG_CASES = [
 ]
 
 
-@pytest.mark.parametrize("resid", ["transform", "direct"])
+@pytest.mark.parametrize("resid", ["fused", "transform", "direct"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", LONG_CASES, ids=lambda c: f"{c[0]}{c[1]}-{c[3]}")
 def test_omp_long_support_residual_paths(fc, case, precision, resid, monkeypatch):
     """Supports long enough for the split least-squares update (t > 64); the
-    residual is forced through the forward transform or the direct sum."""
-    monkeypatch.setenv("FCMP_RESID_RATIO", "0" if resid == "transform" else "1e30")
+    residual is fused into the correlation's first pass (the default where
+    the correlation takes two passes), or forced through the separate forward
+    transform or the direct sum."""
+    if resid == "fused":
+        monkeypatch.delenv("FCMP_RESID_RATIO", raising=False)
+    else:
+        monkeypatch.setenv("FCMP_RESID_RATIO", "0" if resid == "transform" else "1e30")
     checked = 0
     for seed in range(2):
         inst, y, ref = _reference(case, 7100 + seed)

@@ -82,14 +82,19 @@ __global__ void __launch_bounds__(256) rcorr_kernel(RCParams p) {
 
   // ---- A(c, l) from the taps of bucket l, summed in bucket order (a
   // running sum in the tile entry, whatever the chunking); stored conjugated
-  // for the Fourier class (the LDS core runs with the + sign).  This thread
-  // keeps column c = s0 + u of the buckets l = l0 + v lstep.
+  // for the Fourier class (the LDS core runs with the + sign).  A thread
+  // takes bucket l for a run of up to 8 consecutive columns starting at a
+  // multiple of 8.  Fourier twiddles: W(lam, c) = e^{2 pi i lam c / N} is
+  // e^{2 pi i lam a / N} (a = c rounded down to a multiple of 8) times
+  // e^{2 pi i lam / N} applied c - a times in sequence, so each column's
+  // value takes the same operations whatever the tile, and a run costs two
+  // sine/cosine evaluations per tap.
   {
     const double inv_half_n = 2.0 / (double)p.N;
-    const int u = tid & (B - 1);
-    const uint32_t c = (uint32_t)(s0 + u);
-    const int l0 = tid >> logB;
-    const int lstep = nt >> logB;
+    const int logR = min(logB, 3);
+    const int R = 1 << logR;          // columns per run
+    const int logRuns = logB - logR;  // runs per bucket: B / R
+    const int npair = L << logRuns;
     for (int i0 = 0; i0 == 0 || i0 < ntaps; i0 += nt) {
       const int nc = max(0, min(nt, ntaps - i0));
       if (i0 > 0) {
@@ -104,27 +109,42 @@ __global__ void __launch_bounds__(256) rcorr_kernel(RCParams p) {
       }
       __syncthreads();
       const int ie = i0 + nc;
-      for (int l = l0; l < L; l += lstep) {
-        const int a = lds_addr(l * B + u);
-        VR acc = i0 == 0 ? vzero(VR()) : tr[a];
+      for (int pr = tid; pr < npair; pr += nt) {
+        const int l = pr >> logRuns;
+        const int u0 = (pr & ((1 << logRuns) - 1)) << logR;
+        const uint32_t c0 = (uint32_t)(s0 + u0);
+        VR acc[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          acc[j] = (j < R && i0 > 0) ? tr[lds_addr(l * B + u0 + j)] : vzero(VR());
         const int i1 = min(bsl[l + 1], ie);
         for (int i = max(bsl[l], i0); i < i1; ++i) {
           const int li = i - i0;
           const uint32_t lv = (uint32_t)tl[li];
           if constexpr (FFT) {
-            // e^{2 pi i ph / N} evaluated directly (2 ph / N is exact)
-            const uint32_t ph = (lv * c) & maskN;
-            double2 w;
-            sincospi((double)ph * inv_half_n, &w.y, &w.x);
             const double2 xv = tx[li];
-            acc.x += xv.x * w.x + xv.y * w.y;   // conj(x) w
-            acc.y += xv.x * w.y - xv.y * w.x;
+            double2 w, st;
+            sincospi((double)((lv * (c0 & ~7u)) & maskN) * inv_half_n, &w.y, &w.x);
+            sincospi((double)(lv & maskN) * inv_half_n, &st.y, &st.x);
+            for (uint32_t k = 0; k < (c0 & 7u); ++k) w = cmul(w, st);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              if (j < R) {
+                acc[j].x += xv.x * w.x + xv.y * w.y;   // conj(x) w
+                acc[j].y += xv.x * w.y - xv.y * w.x;
+                w = cmul(w, st);
+              }
+            }
           } else {
             const double xv = tx[li];
-            acc += (__popc(lv & mask1 & c) & 1) ? -xv : xv;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (j < R) acc[j] += (__popc(lv & mask1 & (c0 + j)) & 1) ? -xv : xv;
           }
         }
-        tr[a] = acc;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (j < R) tr[lds_addr(l * B + u0 + j)] = acc[j];
       }
     }
   }

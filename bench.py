@@ -228,8 +228,8 @@ def serve_leg(fc, device, count: int, rate_hz: float):
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
-    """HBM bytes per conventional-correlation launch pair (complex64 pass 1 +
-    pass 2 at the workload's grid) from two rocprofv3 --pmc runs of this
+    """HBM bytes per conventional-correlation launch pair (the residual fused
+    with the complex64 first pass, then pass 2, at the workload's grid) from two rocprofv3 --pmc runs of this
     script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by
     what the same counter reads for the plain copy of --copy-probe-mib MiB.
     Written to profiles/pmc_traffic.json with the kernel-source hash."""
@@ -257,7 +257,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
         grids = Counter()
         for r in rows:
             name = r["Kernel_Name"]
-            if "xform_kernel<HIP_vector_type<float, 2u>, true, 1>" in name:
+            if "rcorr_kernel<true, HIP_vector_type<float, 2u>" in name:
                 key = "pass1"
             elif "xform_kernel<HIP_vector_type<float, 2u>, true, 2>" in name:
                 key = "pass2"
@@ -461,7 +461,10 @@ def main():
         "serving": serve,
         "serving_sustained": serve_low,
         "roofline": {
-            "kernel": "conventional correlation (xform pass 1 + pass 2, complex64, B instances)",
+            "kernel": "conventional correlation launch pair, B instances: the FP64 residual "
+                      "fused with the complex64 first pass (rcorr_kernel), then the second "
+                      "pass with the identification (xform_kernel role 2); the residual's "
+                      "time is charged to the correlation",
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,

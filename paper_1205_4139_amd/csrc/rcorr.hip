@@ -166,13 +166,16 @@ __global__ void __launch_bounds__(256) rcorr_kernel(RCParams p) {
 #pragma unroll
   for (int q = 0; q < RC_RMAX; ++q) { rp[q] = -1; rv[q] = vzero(VC()); }
   if (hi > lo) {
+    const int qn = (hi - lo + nt - 1) / nt;   // row slots in use (same for the workgroup)
     int kk[RC_RMAX];
     VR yy[RC_RMAX];
 #pragma unroll
     for (int q = 0; q < RC_RMAX; ++q) {
-      const int e = min(lo + tid + q * nt, hi - 1);
-      kk[q] = ek[e];
-      yy[q] = yv[e];
+      if (q < qn) {
+        const int e = min(lo + tid + q * nt, hi - 1);
+        kk[q] = ek[e];
+        yy[q] = yv[e];
+      }
     }
 #pragma unroll
     for (int q = 0; q < RC_RMAX; ++q) {

@@ -83,14 +83,14 @@ __global__ void __launch_bounds__(256) rcorr_kernel(RCParams p) {
   // ---- A(c, l) from the taps of bucket l, summed in bucket order (a
   // running sum in the tile entry, whatever the chunking); stored conjugated
   // for the Fourier class (the LDS core runs with the + sign).  A thread
-  // takes bucket l for a run of up to 8 consecutive columns starting at a
-  // multiple of 8.  Fourier twiddles: W(lam, c) = e^{2 pi i lam c / N} is
-  // e^{2 pi i lam a / N} (a = c rounded down to a multiple of 8) times
-  // e^{2 pi i lam / N} applied c - a times in sequence, so each column's
-  // value takes the same operations whatever the tile, and a run costs two
-  // sine/cosine evaluations per tap.
+  // takes bucket l for a run of up to 8 consecutive columns.  The twiddle
+  // e^{2 pi i lam c / N} is the two-level table product hi[p >> s] lo[p & (2^s - 1)]
+  // of p = lam c mod N, the same operations whatever the tile; the loads of
+  // four columns are issued together.
   {
-    const double inv_half_n = 2.0 / (double)p.N;
+    const double2* rlo = (const double2*)p.twr_lo;
+    const double2* rhi = (const double2*)p.twr_hi;
+    const uint32_t lomask = (1u << p.twS) - 1u;
     const int logR = min(logB, 3);
     const int R = 1 << logR;          // columns per run
     const int logRuns = logB - logR;  // runs per bucket: B / R
@@ -123,16 +123,24 @@ __global__ void __launch_bounds__(256) rcorr_kernel(RCParams p) {
           const uint32_t lv = (uint32_t)tl[li];
           if constexpr (FFT) {
             const double2 xv = tx[li];
-            double2 w, st;
-            sincospi((double)((lv * (c0 & ~7u)) & maskN) * inv_half_n, &w.y, &w.x);
-            sincospi((double)(lv & maskN) * inv_half_n, &st.y, &st.x);
-            for (uint32_t k = 0; k < (c0 & 7u); ++k) w = cmul(w, st);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              if (j < R) {
-                acc[j].x += xv.x * w.x + xv.y * w.y;   // conj(x) w
-                acc[j].y += xv.x * w.y - xv.y * w.x;
-                w = cmul(w, st);
+            for (int h = 0; h < 8; h += 4) {
+              if (h < R) {
+                double2 wh[4], wl[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  const uint32_t ph = (lv * (c0 + (uint32_t)(h + j))) & maskN;
+                  wh[j] = rhi[ph >> p.twS];
+                  wl[j] = rlo[ph & lomask];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                  if (h + j < R) {
+                    const double2 w = cmul(wh[j], wl[j]);
+                    acc[h + j].x += xv.x * w.x + xv.y * w.y;   // conj(x) w
+                    acc[h + j].y += xv.x * w.y - xv.y * w.x;
+                  }
+                }
               }
             }
           } else {

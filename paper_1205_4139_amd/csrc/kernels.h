@@ -175,7 +175,7 @@ struct LParams {
   int64_t inst_part, inst_c, inst_h0, inst_W, inst_z, inst_x, inst_lam, inst_excl;
   // scratch for the split update (nullable: then one workgroup per instance)
   void* wbuf; int64_t inst_wbuf;          // w = W g, K values
-  void* vpart; int64_t inst_vpart;        // LS_MAX_GROUPS partial rows of w^H W, K values each
+  void* vpart; int64_t inst_vpart;        // ls_split_groups(K) partial rows of w^H W, K values each
   int64_t vpart_stride;
   const int32_t* Kv;       // nullable: per-instance K; an instance whose K
                            // selections are made is marked done at t = K + 1
@@ -187,7 +187,7 @@ struct LParams {
 };
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st);
 int ls_split_groups(int t);   // workgroups per instance used at iteration t
-constexpr int LS_MAX_GROUPS = 32;   // partial rows of w^H W kept per instance
+constexpr int LS_MAX_GROUPS = 256;  // most partial rows of w^H W (long supports)
 
 // ------------------------------------------------------------------ utilities
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

@@ -132,7 +132,7 @@ void plan_layout(fcmp_plan& P, char* base) {
   P.z = cv.take_bytes(n * P.sK * wb);
   P.W = cv.take_bytes(n * P.sW * wb);
   P.wbuf = cv.take_bytes(n * P.sK * wb);
-  P.vpart = cv.take_bytes(n * LS_MAX_GROUPS * P.sK * wb);
+  P.vpart = cv.take_bytes(n * ls_split_groups((int)P.shape.K) * P.sK * wb);
   P.status = cv.take<Status>(n);
   if (P.opt.algorithm != FCMP_OMP) {
     const int64_t K = P.shape.K, N = P.shape.N;
@@ -427,7 +427,7 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
   lp.inst_part = P.sP; lp.inst_c = P.sN; lp.inst_h0 = P.sN; lp.inst_W = P.sW;
   lp.inst_z = P.sK; lp.inst_x = P.sK; lp.inst_lam = P.sK; lp.inst_excl = P.sE;
   lp.wbuf = P.wbuf; lp.inst_wbuf = P.sK;
-  lp.vpart = P.vpart; lp.inst_vpart = LS_MAX_GROUPS * P.sK; lp.vpart_stride = P.sK;
+  lp.vpart = P.vpart; lp.inst_vpart = ls_split_groups((int)K) * P.sK; lp.vpart_stride = P.sK;
   lp.Kv = P.Kv;
   if (P.fused) {
     lp.ord = P.ord; lp.bstart = P.bst;

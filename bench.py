@@ -294,7 +294,7 @@ def main():
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--fast-steps", type=int, default=1)
     ap.add_argument("--plain", type=int, default=6, help="single-instance solves to time")
-    ap.add_argument("--cpu-iters", type=int, default=96)
+    ap.add_argument("--cpu-iters", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")

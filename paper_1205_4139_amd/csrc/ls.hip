@@ -17,7 +17,7 @@
 namespace fcmp {
 
 constexpr int L_THREADS = 256;
-constexpr int L_KPT = 16;     // columns per thread in the w^H W product: K <= 4096
+constexpr int L_KPT = 16;     // most columns per thread in the w^H W product: K <= 4096
 constexpr int L_RB = 4;       // rows per wave in w = W g (independent loads in flight)
 constexpr int L_VB = 8;       // rows per step in w^H W (independent loads in flight)
 
@@ -53,27 +53,30 @@ __device__ __forceinline__ void ls_rows_wg(const Wd* W, const Wd* g, int i0, int
 
 // acc[q] += sum over rows i = i_first, i_first + step, ... (< n) of
 // conj(w_i) W(i, k) for k = tid + q L_THREADS <= i, rows in increasing order,
-// L_VB rows per step with their loads issued together.
-template <bool FOURIER, class Wd>
+// VB rows per step with their loads issued together.  KPT (columns per
+// thread, a compile-time bound on nq) sizes the accumulators, so short
+// supports keep few registers; neither KPT nor VB changes the order of the
+// additions.
+template <bool FOURIER, int KPT, int VB, class Wd>
 __device__ __forceinline__ void ls_rows_wh(const Wd* W, const Wd* w, int i_first, int step, int n,
                                            int nq, int tid, Wd* acc) {
   int i = i_first;
-  for (; i + (L_VB - 1) * step < n; i += L_VB * step) {
-    Wd wv[L_VB];
+  for (; i + (VB - 1) * step < n; i += VB * step) {
+    Wd wv[VB];
 #pragma unroll
-    for (int u = 0; u < L_VB; ++u) wv[u] = w[i + u * step];
+    for (int u = 0; u < VB; ++u) wv[u] = w[i + u * step];
 #pragma unroll
-    for (int q = 0; q < L_KPT; ++q) {
+    for (int q = 0; q < KPT; ++q) {
       const int k = tid + q * L_THREADS;
       if (q < nq) {
-        Wd a[L_VB];
+        Wd a[VB];
 #pragma unroll
-        for (int u = 0; u < L_VB; ++u) {
+        for (int u = 0; u < VB; ++u) {
           const int r = i + u * step;
           a[u] = k <= r ? W[(int64_t)r * (r + 1) / 2 + k] : vzero(Wd());
         }
 #pragma unroll
-        for (int u = 0; u < L_VB; ++u) {
+        for (int u = 0; u < VB; ++u) {
           const int r = i + u * step;
           if (k <= r) {
             if constexpr (FOURIER) { const double2 t = cmulc(wv[u], a[u]); acc[q].x += t.x; acc[q].y += t.y; }
@@ -87,7 +90,7 @@ __device__ __forceinline__ void ls_rows_wh(const Wd* W, const Wd* w, int i_first
     const Wd* Wi = W + (int64_t)i * (i + 1) / 2;
     const Wd wi = w[i];
 #pragma unroll
-    for (int q = 0; q < L_KPT; ++q) {
+    for (int q = 0; q < KPT; ++q) {
       const int k = tid + q * L_THREADS;
       if (q < nq && k <= i) {
         if constexpr (FOURIER) { const double2 t = cmulc(wi, Wi[k]); acc[q].x += t.x; acc[q].y += t.y; }
@@ -117,7 +120,7 @@ __device__ __forceinline__ void tap_order_insert(const LParams& p, int inst, int
     bnew[b] = (n > 0 ? bold[b] : 0) + (b > key ? 1 : 0);
 }
 
-template <bool FOURIER>
+template <bool FOURIER, int KPT>
 __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -192,15 +195,15 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
   const double invd = 1.0 / d;
 
   // ---- new row of W: v_k = -(sum_{i>=k} conj(w_i) W(i,k)) / d
-  Wd acc[L_KPT];
+  Wd acc[KPT];
 #pragma unroll
-  for (int q = 0; q < L_KPT; ++q) acc[q] = vzero(Wd());
+  for (int q = 0; q < KPT; ++q) acc[q] = vzero(Wd());
   const int nq = (n + L_THREADS - 1) / L_THREADS;
-  ls_rows_wh<FOURIER>(W, w, 0, 1, n, nq, tid, acc);
+  ls_rows_wh<FOURIER, KPT, L_VB>(W, w, 0, 1, n, nq, tid, acc);
   __syncthreads();   // everyone is done reading g
   Wd* Wn = W + (int64_t)n * (n + 1) / 2;
 #pragma unroll
-  for (int q = 0; q < L_KPT; ++q) {
+  for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * L_THREADS;
     if (k < n) {
       Wd v;
@@ -322,7 +325,7 @@ __device__ __forceinline__ bool ls_d(const LParams& p, int inst, int n, double* 
   return true;
 }
 
-template <bool FOURIER>
+template <bool FOURIER, int KPT>
 __global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
   __shared__ double dred[16];
@@ -338,14 +341,14 @@ __global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
   }
   const Wd* w = (const Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
   const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
-  Wd acc[L_KPT];
+  Wd acc[KPT];
 #pragma unroll
-  for (int q = 0; q < L_KPT; ++q) acc[q] = vzero(Wd());
+  for (int q = 0; q < KPT; ++q) acc[q] = vzero(Wd());
   const int nq = (n + L_THREADS - 1) / L_THREADS;
-  ls_rows_wh<FOURIER>(W, w, gid, G, n, nq, tid, acc);
+  ls_rows_wh<FOURIER, KPT, L_VB>(W, w, gid, G, n, nq, tid, acc);
   Wd* vp = (Wd*)p.vpart + (int64_t)inst * p.inst_vpart + (int64_t)gid * p.vpart_stride;
 #pragma unroll
-  for (int q = 0; q < L_KPT; ++q) {
+  for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * L_THREADS;
     if (q < nq && k < n) vp[k] = acc[q];
   }
@@ -419,36 +422,63 @@ int ls_split_groups(int t) {
   return G;
 }
 
+// Columns per thread of the w^H W product, rounded up to a power of two.
+static int ls_kpt(int n) {
+  const int nq = (n + L_THREADS - 1) / L_THREADS;
+  int k = 1;
+  while (k < nq) k *= 2;
+  return k;
+}
+
+template <bool FOURIER, int KPT>
+static void launch_ls_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
+                          hipStream_t st) {
+  if (split) {
+    hipLaunchKernelGGL((ls_b_kernel<FOURIER, KPT>), dim3(G, ninst), dim3(L_THREADS), 0, st, p);
+  } else {
+    raise_lds_limit((const void*)ls_kernel<FOURIER, KPT>, lds);
+    hipLaunchKernelGGL((ls_kernel<FOURIER, KPT>), dim3(ninst), dim3(L_THREADS), lds, st, p);
+  }
+}
+
+template <bool FOURIER>
+static void launch_ls_by_kpt(const LParams& p, int ninst, int G, bool split, size_t lds, int n,
+                             hipStream_t st) {
+  switch (ls_kpt(n)) {
+    case 1: launch_ls_kpt<FOURIER, 1>(p, ninst, G, split, lds, st); break;
+    case 2: launch_ls_kpt<FOURIER, 2>(p, ninst, G, split, lds, st); break;
+    case 4: launch_ls_kpt<FOURIER, 4>(p, ninst, G, split, lds, st); break;
+    case 8: launch_ls_kpt<FOURIER, 8>(p, ninst, G, split, lds, st); break;
+    default: launch_ls_kpt<FOURIER, 16>(p, ninst, G, split, lds, st); break;
+  }
+}
+
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st) {
   const int G = ls_split_groups(p.t);
+  const int n = p.t - 1;
+  if (n > L_KPT * L_THREADS) return hipErrorInvalidValue;
   if (G > 1 && p.wbuf && p.vpart) {
-    const int n = p.t - 1;
     const size_t wb = p.fourier ? 16 : 8;
     const size_t lds_a = (size_t)n * wb + 16;
     const int cblocks = (n + L_THREADS - 1) / L_THREADS;
     if (p.fourier) {
       raise_lds_limit((const void*)ls_a_kernel<true>, lds_a);
       hipLaunchKernelGGL(ls_a_kernel<true>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
-      hipLaunchKernelGGL(ls_b_kernel<true>, dim3(G, ninst), dim3(L_THREADS), 0, st, p);
+      launch_ls_by_kpt<true>(p, ninst, G, true, 0, n, st);
       hipLaunchKernelGGL(ls_c_kernel<true>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
     } else {
       raise_lds_limit((const void*)ls_a_kernel<false>, lds_a);
       hipLaunchKernelGGL(ls_a_kernel<false>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
-      hipLaunchKernelGGL(ls_b_kernel<false>, dim3(G, ninst), dim3(L_THREADS), 0, st, p);
+      launch_ls_by_kpt<false>(p, ninst, G, true, 0, n, st);
       hipLaunchKernelGGL(ls_c_kernel<false>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
     }
     return hipGetLastError();
   }
-  const int n = p.t - 1 > 0 ? p.t - 1 : 1;
+  const int n1 = n > 0 ? n : 1;
   const size_t wb = p.fourier ? 16 : 8;
-  const size_t lds = 2 * n * wb + (size_t)n * 4 + 16;
-  if (p.fourier) {
-    raise_lds_limit((const void*)ls_kernel<true>, lds);
-    hipLaunchKernelGGL(ls_kernel<true>, dim3(ninst), dim3(L_THREADS), lds, st, p);
-  } else {
-    raise_lds_limit((const void*)ls_kernel<false>, lds);
-    hipLaunchKernelGGL(ls_kernel<false>, dim3(ninst), dim3(L_THREADS), lds, st, p);
-  }
+  const size_t lds = 2 * n1 * wb + (size_t)n1 * 4 + 16;
+  if (p.fourier) launch_ls_by_kpt<true>(p, ninst, 1, false, lds, n, st);
+  else launch_ls_by_kpt<false>(p, ninst, 1, false, lds, n, st);
   return hipGetLastError();
 }
 

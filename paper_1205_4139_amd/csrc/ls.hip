@@ -19,6 +19,7 @@ namespace fcmp {
 constexpr int L_THREADS = 256;
 constexpr int L_KPT = 16;     // most columns per thread in the w^H W product: K <= 4096
 constexpr int L_RB = 4;       // rows per wave in w = W g (independent loads in flight)
+constexpr int L_KU = 2;       // lane-strided column chunks per step in w = W g
 constexpr int L_VB = 8;       // rows per step in w^H W (independent loads in flight)
 
 // w_i = sum_{k <= i} W(i,k) g_k for the rows i = i0 .. i0+L_RB-1 (< n) of one
@@ -31,15 +32,35 @@ __device__ __forceinline__ void ls_rows_wg(const Wd* W, const Wd* g, int i0, int
 #pragma unroll
   for (int u = 0; u < L_RB; ++u) s[u] = vzero(Wd());
   const int imax = min(i0 + L_RB, n) - 1;
-  for (int k = lane; k <= imax; k += 64) {
-    const Wd gk = g[k];
+  // L_KU lane-strided chunks of k per step, their loads (clamped to valid
+  // entries) issued together; each lane still adds its k in increasing order
+  for (int k0 = lane; k0 <= imax; k0 += 64 * L_KU) {
+    Wd a[L_KU][L_RB], gk[L_KU];
 #pragma unroll
-    for (int u = 0; u < L_RB; ++u) {
-      const int i = i0 + u;
-      if (i <= imax && k <= i) {
-        const Wd a = W[(int64_t)i * (i + 1) / 2 + k];
-        if constexpr (FOURIER) { const double2 t = cmul(a, gk); s[u].x += t.x; s[u].y += t.y; }
-        else s[u] += a * gk;
+    for (int v = 0; v < L_KU; ++v) {
+      const int kc = min(k0 + 64 * v, imax);
+      gk[v] = g[kc];
+#pragma unroll
+      for (int u = 0; u < L_RB; ++u) {
+        const int i = min(i0 + u, imax);
+        a[v][u] = W[(int64_t)i * (i + 1) / 2 + min(kc, i)];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < L_KU; ++v) {
+      const int k = k0 + 64 * v;
+#pragma unroll
+      for (int u = 0; u < L_RB; ++u) {
+        const int i = i0 + u;
+        if (k <= imax && i <= imax && k <= i) {
+          if constexpr (FOURIER) {
+            const double2 t = cmul(a[v][u], gk[v]);
+            s[u].x += t.x;
+            s[u].y += t.y;
+          } else {
+            s[u] += a[v][u] * gk[v];
+          }
+        }
       }
     }
   }
@@ -376,8 +397,19 @@ __global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int G) {
   const Wd* vp = (const Wd*)p.vpart + (int64_t)inst * p.inst_vpart;
   const int k = cb * L_THREADS + tid;
   if (k < n) {
+    // the G partials in order, eight loads in flight at a time
     Wd s = vzero(Wd());
-    for (int q = 0; q < G; ++q) {
+    int q = 0;
+    for (; q + 8 <= G; q += 8) {
+      Wd a[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) a[v] = vp[(int64_t)(q + v) * p.vpart_stride + k];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        if constexpr (FOURIER) { s.x += a[v].x; s.y += a[v].y; } else s += a[v];
+      }
+    }
+    for (; q < G; ++q) {
       const Wd a = vp[(int64_t)q * p.vpart_stride + k];
       if constexpr (FOURIER) { s.x += a.x; s.y += a.y; } else s += a;
     }

@@ -383,6 +383,15 @@ def main():
         methods[meth] = {"ms_per_step": round(t * 1e3, 3), "solves_per_s": round(B / t, 3)}
         print(f"[bench] {meth}: {t*1e3:.2f} ms/step", file=sys.stderr, flush=True)
 
+    # ---- fast correlation gathering only half of the kernel vector (its
+    # conjugate symmetry), same batch
+    if args.fast_steps > 0:
+        t = time_steps(lambda: plan.solve(ys, method="fast", flags=fc.FLAG_HALF_KERNEL),
+                       args.fast_steps, 0)
+        methods["fast_half_kernel"] = {"ms_per_step": round(t * 1e3, 3),
+                                       "solves_per_s": round(B / t, 3)}
+        print(f"[bench] fast, half kernel vector: {t*1e3:.2f} ms/step", file=sys.stderr, flush=True)
+
     # ---- the same conventional step replayed from one captured graph
     yl = [ys[i] for i in range(B)]
     gp = fc.BatchPlan([("F", N, M, K, i.omega) for i in insts], method="conventional",

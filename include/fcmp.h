@@ -116,6 +116,14 @@ typedef struct {
  * floating-point gathers.  This flag makes a solve gather the floating-point
  * copy instead. */
 #define FCMP_FLAG_FLOAT_KERNEL 4u
+/* Fourier plans, fast correlation (eq. (kernelsumOMP)): gather only the half
+ * c(0..N/2) of the kernel vector and use c(m) = conj(c(N - m)) above N/2,
+ * the conjugate symmetry of the Fourier kernel vector (Sec. III-B: it is the
+ * DFT of the real 0/1 mask of Omega), so a correlation touches half of c.  The
+ * values above N/2 are the conjugated mirror entries rather than the stored
+ * ones, so results agree with the full gathers to rounding, not bit for bit.
+ * Ignored for the Hadamard class and by the persistent batch kernel. */
+#define FCMP_FLAG_HALF_KERNEL 8u
 
 typedef struct {
   int32_t iterations;        /* OMP: selections made; SP/CoSaMP: outer iterations */

@@ -379,6 +379,7 @@ def profile_read(reset=True) -> dict:
 
 FLAG_NO_PERSISTENT = 2
 FLAG_FLOAT_KERNEL = 4
+FLAG_HALF_KERNEL = 8
 
 
 def batch_solve(problems, ys, algorithm="omp", method="conventional", precision="fp64",

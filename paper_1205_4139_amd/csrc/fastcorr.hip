@@ -35,6 +35,8 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
   if (p.status && p.status[inst].done) return;
   const int tid = threadIdx.x;
   const uint32_t mask = (uint32_t)p.N - 1u;
+  const bool half = p.c_half != 0;
+  const uint32_t half_n = (uint32_t)p.N >> 1;
   const int64_t jb = (int64_t)blockIdx.x * (F_THREADS * JPT) + tid;
   const Wd* h0 = (const Wd*)p.h0 + (int64_t)inst * p.inst_h0;
   const VC* c = (const VC*)p.c + (int64_t)inst * p.inst_c;
@@ -65,7 +67,16 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
 #pragma unroll
         for (int u = 0; u < JPT; ++u) {
           const uint32_t j = (uint32_t)(jb + u * F_THREADS) & mask;
-          cv[q][u] = c[perm_index(FOURIER, j, l, mask)];
+          const uint32_t m = perm_index(FOURIER, j, l, mask);
+          if constexpr (FOURIER) {
+            // conjugate symmetry: c(m) = conj(c(N - m)); a wave crosses N/2 at
+            // most once per tap, so the two halves are read as contiguous runs
+            const bool up = half && m > half_n;
+            cv[q][u] = c[up ? p.N - m : m];
+            if (up) cv[q][u].y = -cv[q][u].y;
+          } else {
+            cv[q][u] = c[m];
+          }
         }
       }
 #pragma unroll

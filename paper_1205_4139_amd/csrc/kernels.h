@@ -141,6 +141,7 @@ struct FParams {
   int fourier;
   int c_kind;              // VKind of the stored kernel vector
   int c_int16;             // Hadamard: c holds the integers N c as int16 (c_kind ignored)
+  int c_half;              // Fourier: read c(m) for m > N/2 as conj(c(N - m))
   double cscale;           //   and c(j) = cscale * (N c)(j), cscale = 1/N (exact)
   const void* h0;          // FP64 (wide)
   const void* c;

@@ -318,6 +318,7 @@ int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
   FParams fp{};
   fp.N = (int)P.shape.N; fp.logN = P.g.logN; fp.fourier = P.g.fourier; fp.c_kind = P.pk;
   fp.h0 = P.h0; fp.c = P.cp; fp.lam = P.lam; fp.x = P.x; fp.ntaps = t - 1;
+  fp.c_half = (P.g.fourier && (P.cur_flags & FCMP_FLAG_HALF_KERNEL)) ? 1 : 0;
   if (P.ci16 && !(P.cur_flags & FCMP_FLAG_FLOAT_KERNEL)) {
     fp.c = P.ci16;
     fp.c_int16 = 1;

@@ -110,7 +110,7 @@ def test_options_validation(fc):
         _q(fc, precision=5)
     p, om = fc.make_problem("H", 1024, 256, 16, np.arange(256) * 4)
     o = fc.make_options()
-    o.flags = 8
+    o.flags = 16   # no such flag
     n = ctypes.c_size_t(0)
     assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID
 

@@ -201,6 +201,75 @@ def test_lockstep_plan_with_mixed_m_and_k(fc, precision, monkeypatch):
             assert np.linalg.norm(to_np(xs[k]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [("F", 32768, "cgauss", [(8192, 120), (3000, 70), (6000, 30), (4096, 90)]),
+                                  ("H", 65536, "gauss", [(8192, 100), (5000, 70), (7000, 40)])],
+                         ids=["F32768", "H65536"])
+def test_fused_residual_plan_with_mixed_m_and_k(fc, case, precision, monkeypatch):
+    """The residual fused into the correlation's first pass, in one lockstep
+    plan whose problems have different M and K: problems that are done stop
+    while the others continue (their tap order is no longer maintained), and
+    every problem equals its solve alone bit for bit and the oracle on
+    certified instances."""
+    monkeypatch.delenv("FCMP_RESID_RATIO", raising=False)
+    cls, N, law, shapes = case
+    insts = [instancegen.draw_instance(cls, N, M, K, law, 30.0, 8750 + i)
+             for i, (M, K) in enumerate(shapes)]
+    ys = [oracle.problem.instance_measure(i, tier="transform") for i in insts]
+    probs = [(i.cls, i.N, i.M, i.K, i.omega) for i in insts]
+    sups, xs, stats = fc.batch_solve(probs, [to_dev(y) for y in ys], precision=precision,
+                                     flags=fc.FLAG_NO_PERSISTENT)
+    checked = 0
+    for k, (inst, y) in enumerate(zip(insts, ys)):
+        assert stats[k].iterations == inst.K
+        alone = fc.solve(inst.cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y),
+                         precision=precision)
+        assert np.array_equal(to_np(alone.support), to_np(sups[k])), k
+        assert np.array_equal(to_np(alone.x), to_np(xs[k])), k
+        ref = oracle.omp(oracle.make_operator(inst.cls, inst.N, inst.omega, "transform"), y, inst.K)
+        if certify.certified(ref, precision):
+            assert list(to_np(sups[k])) == list(ref.support)
+            assert np.linalg.norm(to_np(xs[k]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+            checked += 1
+    assert checked >= 1
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fast_correlation_half_kernel_vector(fc, precision):
+    """Fast correlation gathering only c(0..N/2), with c(m) = conj(c(N - m))
+    above N/2: the oracle's support on certified instances and x to 1e-10,
+    and x within rounding of the full-table solve; the flag leaves the
+    Hadamard class unchanged bit for bit."""
+    import torch
+    data = _insts("F", 65536, 8192, 60, "cgauss", 30.0, 3, 8950)
+    plan = fc.Plan("F", 65536, 8192, 60, [d[0].omega for d in data], precision=precision,
+                   method="fast")
+    ys = torch.stack([to_dev(d[1]) for d in data])
+    s_full, x_full, _ = plan.solve(ys, method="fast")
+    s_full, x_full = to_np(s_full).copy(), to_np(x_full).copy()
+    s_half, x_half, st = plan.solve(ys, method="fast", flags=fc.FLAG_HALF_KERNEL, stats=True)
+    s_half, x_half = to_np(s_half), to_np(x_half)
+    checked = 0
+    for b, (inst, y) in enumerate(data):
+        assert st[b].iterations == 60
+        ref = oracle.omp(oracle.make_operator("F", 65536, inst.omega, "transform"), y, 60)
+        if certify.certified(ref, precision):
+            assert list(s_half[b]) == list(ref.support)
+            assert np.linalg.norm(x_half[b] - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+            checked += 1
+        if list(s_half[b]) == list(s_full[b]):
+            assert np.linalg.norm(x_half[b] - x_full[b]) <= 1e-12 * np.linalg.norm(x_full[b])
+    assert checked >= 1
+    hd = _insts("H", 4096, 1000, 37, "gauss", 40.0, 2, 8960)
+    hplan = fc.Plan("H", 4096, 1000, 37, [d[0].omega for d in hd], precision=precision,
+                    method="fast")
+    hy = torch.stack([to_dev(d[1]) for d in hd])
+    a, ax, _ = hplan.solve(hy, method="fast")
+    a, ax = to_np(a).copy(), to_np(ax).copy()
+    b2, bx, _ = hplan.solve(hy, method="fast", flags=fc.FLAG_HALF_KERNEL)
+    assert np.array_equal(a, to_np(b2)) and np.array_equal(ax, to_np(bx))
+
+
 def test_autotuned_adaptive_switch(fc, tmp_path):
     """The autotuner records a measured switch iteration; adaptive solves with
     switch_t = 0 then use it, bit for bit as when it is passed explicitly, and

@@ -272,8 +272,9 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
 // ---------------------------------------------------------------------------
 // The same update split over G workgroups per instance for long supports:
 //   ls_a: identification, Gram column, w = W g (rows cyclic over G*4 waves)
-//   ls_b: d, and partial sums of w^H W over the rows i = gid (mod G)
-//   ls_c: v = -(sum over the G partials, in order)/d, new row of W, z and x
+//   ls_b: partial sums of w^H W over the rows i = gid (mod G)
+//   ls_c: d (and the breakdown test), v = -(sum over the G partials, in
+//         order)/d, new row of W, z and x
 // Every reduction has a fixed order, so results depend on t only.
 template <bool FOURIER>
 __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
@@ -349,17 +350,12 @@ __device__ __forceinline__ bool ls_d(const LParams& p, int inst, int n, double* 
 template <bool FOURIER, int KPT>
 __global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
-  __shared__ double dred[16];
   const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
   Status* st = p.status + inst;
   if (st->done) return;
   const int tid = threadIdx.x;
   const int n = p.t - 1;
-  double invd, wzr, wzi;
-  if (!ls_d<FOURIER>(p, inst, n, dred, invd, wzr, wzi)) {
-    if (gid == 0 && tid == 0) { st->numeric = 1; st->done = 1; }
-    return;
-  }
+  // the partial sums do not need d: the breakdown test is left to ls_c
   const Wd* w = (const Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
   const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
   Wd acc[KPT];
@@ -385,7 +381,10 @@ __global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int G) {
   const int tid = threadIdx.x;
   const int n = p.t - 1;
   double invd, wzr, wzi;
-  if (!ls_d<FOURIER>(p, inst, n, dred, invd, wzr, wzi)) return;   // ls_b flagged it
+  if (!ls_d<FOURIER>(p, inst, n, dred, invd, wzr, wzi)) {
+    if (cb == 0 && threadIdx.x == 0) { st->numeric = 1; st->done = 1; }
+    return;
+  }
   const uint32_t j = (uint32_t)st->cur_j;
   Wd b = ((const Wd*)p.h0 + (int64_t)inst * p.inst_h0)[j];
   Wd zt;
@@ -463,55 +462,54 @@ static int ls_kpt(int n) {
 }
 
 template <bool FOURIER, int KPT>
-static void launch_ls_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
-                          hipStream_t st) {
+static hipError_t launch_ls_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
+                                hipStream_t st) {
   if (split) {
     hipLaunchKernelGGL((ls_b_kernel<FOURIER, KPT>), dim3(G, ninst), dim3(L_THREADS), 0, st, p);
   } else {
-    raise_lds_limit((const void*)ls_kernel<FOURIER, KPT>, lds);
+    hipError_t e = raise_lds_limit((const void*)ls_kernel<FOURIER, KPT>, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((ls_kernel<FOURIER, KPT>), dim3(ninst), dim3(L_THREADS), lds, st, p);
+  }
+  return hipGetLastError();
+}
+
+template <bool FOURIER>
+static hipError_t launch_ls_by_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
+                                   int n, hipStream_t st) {
+  switch (ls_kpt(n)) {
+    case 1: return launch_ls_kpt<FOURIER, 1>(p, ninst, G, split, lds, st);
+    case 2: return launch_ls_kpt<FOURIER, 2>(p, ninst, G, split, lds, st);
+    case 4: return launch_ls_kpt<FOURIER, 4>(p, ninst, G, split, lds, st);
+    case 8: return launch_ls_kpt<FOURIER, 8>(p, ninst, G, split, lds, st);
+    default: return launch_ls_kpt<FOURIER, 16>(p, ninst, G, split, lds, st);
   }
 }
 
 template <bool FOURIER>
-static void launch_ls_by_kpt(const LParams& p, int ninst, int G, bool split, size_t lds, int n,
-                             hipStream_t st) {
-  switch (ls_kpt(n)) {
-    case 1: launch_ls_kpt<FOURIER, 1>(p, ninst, G, split, lds, st); break;
-    case 2: launch_ls_kpt<FOURIER, 2>(p, ninst, G, split, lds, st); break;
-    case 4: launch_ls_kpt<FOURIER, 4>(p, ninst, G, split, lds, st); break;
-    case 8: launch_ls_kpt<FOURIER, 8>(p, ninst, G, split, lds, st); break;
-    default: launch_ls_kpt<FOURIER, 16>(p, ninst, G, split, lds, st); break;
-  }
+static hipError_t launch_ls_split(const LParams& p, int ninst, int G, int n, hipStream_t st) {
+  const size_t lds_a = (size_t)n * (FOURIER ? 16 : 8) + 16;
+  const int cblocks = (n + L_THREADS - 1) / L_THREADS;
+  hipError_t e = raise_lds_limit((const void*)ls_a_kernel<FOURIER>, lds_a);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ls_a_kernel<FOURIER>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
+  if ((e = launch_ls_by_kpt<FOURIER>(p, ninst, G, true, 0, n, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(ls_c_kernel<FOURIER>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
+  return hipGetLastError();
 }
 
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st) {
   const int G = ls_split_groups(p.t);
   const int n = p.t - 1;
   if (n > L_KPT * L_THREADS) return hipErrorInvalidValue;
-  if (G > 1 && p.wbuf && p.vpart) {
-    const size_t wb = p.fourier ? 16 : 8;
-    const size_t lds_a = (size_t)n * wb + 16;
-    const int cblocks = (n + L_THREADS - 1) / L_THREADS;
-    if (p.fourier) {
-      raise_lds_limit((const void*)ls_a_kernel<true>, lds_a);
-      hipLaunchKernelGGL(ls_a_kernel<true>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
-      launch_ls_by_kpt<true>(p, ninst, G, true, 0, n, st);
-      hipLaunchKernelGGL(ls_c_kernel<true>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
-    } else {
-      raise_lds_limit((const void*)ls_a_kernel<false>, lds_a);
-      hipLaunchKernelGGL(ls_a_kernel<false>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
-      launch_ls_by_kpt<false>(p, ninst, G, true, 0, n, st);
-      hipLaunchKernelGGL(ls_c_kernel<false>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
-    }
-    return hipGetLastError();
-  }
+  if (G > 1 && p.wbuf && p.vpart)
+    return p.fourier ? launch_ls_split<true>(p, ninst, G, n, st)
+                     : launch_ls_split<false>(p, ninst, G, n, st);
   const int n1 = n > 0 ? n : 1;
   const size_t wb = p.fourier ? 16 : 8;
   const size_t lds = 2 * n1 * wb + (size_t)n1 * 4 + 16;
-  if (p.fourier) launch_ls_by_kpt<true>(p, ninst, 1, false, lds, n, st);
-  else launch_ls_by_kpt<false>(p, ninst, 1, false, lds, n, st);
-  return hipGetLastError();
+  return p.fourier ? launch_ls_by_kpt<true>(p, ninst, 1, false, lds, n, st)
+                   : launch_ls_by_kpt<false>(p, ninst, 1, false, lds, n, st);
 }
 
 }  // namespace fcmp

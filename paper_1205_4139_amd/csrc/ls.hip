@@ -282,19 +282,25 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Sel red[16];
   const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int n = p.t - 1;
   Status* st = p.status + inst;
+  // loads whose addresses do not depend on the outcome go out together: the
+  // status, the first partials and the first selected columns
+  const int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
+  const Sel* part = p.partial + (int64_t)inst * p.inst_part;
+  const Sel s0 = tid < p.npart ? part[tid] : Sel{-1.0, -1};
+  const int32_t l0 = tid < n ? lam[tid] : 0;
   if (st->done) return;
   if (p.Kv && p.t > p.Kv[inst]) {   // its K selections are made
     if (gid == 0 && threadIdx.x == 0) st->done = 1;
     return;
   }
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n = p.t - 1;
   Wd* g = (Wd*)smem_raw;
-  const Sel* part = p.partial + (int64_t)inst * p.inst_part;
   double bk = -1.0;
   int64_t bi = -1;
-  for (int e = tid; e < p.npart; e += L_THREADS) {
+  if (s0.idx >= 0) { bk = s0.key; bi = s0.idx; }
+  for (int e = tid + L_THREADS; e < p.npart; e += L_THREADS) {
     const Sel s = part[e];
     if (s.idx >= 0 && sel_better(s.key, s.idx, bk, bi)) { bk = s.key; bi = s.idx; }
   }
@@ -309,11 +315,12 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
     st->last_key = best.key;
   }
   const uint32_t mask = (uint32_t)p.N - 1u;
-  const int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
   const Wd* c64 = (const Wd*)p.c64 + (int64_t)inst * p.inst_c;
   const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
   Wd* wout = (Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
-  for (int i = tid; i < n; i += L_THREADS) g[i] = c64[perm_index(FOURIER, (uint32_t)lam[i], j, mask)];
+  if (tid < n) g[tid] = c64[perm_index(FOURIER, (uint32_t)l0, j, mask)];
+  for (int i = tid + L_THREADS; i < n; i += L_THREADS)
+    g[i] = c64[perm_index(FOURIER, (uint32_t)lam[i], j, mask)];
   __syncthreads();
   const int nw = G * (L_THREADS / 64);
   for (int i0 = (gid * (L_THREADS / 64) + wave) * L_RB; i0 < n; i0 += nw * L_RB)

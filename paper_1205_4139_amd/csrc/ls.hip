@@ -497,9 +497,15 @@ template <bool FOURIER>
 static hipError_t launch_ls_split(const LParams& p, int ninst, int G, int n, hipStream_t st) {
   const size_t lds_a = (size_t)n * (FOURIER ? 16 : 8) + 16;
   const int cblocks = (n + L_THREADS - 1) / L_THREADS;
+  // w = W g: with few instances, enough workgroups that every wave takes one
+  // group of L_RB rows, up to about 1024 in all (the row-to-wave assignment
+  // does not change any sum)
+  const int waves = L_THREADS / 64;
+  const int Ga = std::max(G, std::min((n + L_RB * waves - 1) / (L_RB * waves),
+                                      (1024 + ninst - 1) / ninst));
   hipError_t e = raise_lds_limit((const void*)ls_a_kernel<FOURIER>, lds_a);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ls_a_kernel<FOURIER>, dim3(G, ninst), dim3(L_THREADS), lds_a, st, p);
+  hipLaunchKernelGGL(ls_a_kernel<FOURIER>, dim3(Ga, ninst), dim3(L_THREADS), lds_a, st, p);
   if ((e = launch_ls_by_kpt<FOURIER>(p, ninst, G, true, 0, n, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(ls_c_kernel<FOURIER>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
   return hipGetLastError();

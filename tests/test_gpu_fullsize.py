@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden",
                       "omp_fourier_n65536_m16384_k256_seed2000.json")
 N, M, K = 65536, 16384, 256
-BATCH = 128          # the benchmark's lockstep plan
+BATCH = 256          # the benchmark's lockstep plan
 
 
 @pytest.fixture(scope="module")
@@ -32,10 +32,10 @@ def fc():
 
 
 @pytest.mark.parametrize("method", ["conventional", "adaptive"])
-def test_fourier_65536_lockstep_plan_128(fc, method):
-    """The benchmark's plan: 128 instances (seeds 2000..2127), complex64/FP32
+def test_fourier_65536_lockstep_plan_256(fc, method):
+    """The benchmark's plan: 256 instances (seeds 2000..2255), complex64/FP32
     correlation.  Instance 0 reproduces the stored oracle solve (support
-    exactly: its gaps are certified at FP32; x to 1e-10); instances 0 and 127
+    exactly: its gaps are certified at FP32; x to 1e-10); instances 0 and 255
     solved alone give bit-identical results; every instance runs K steps."""
     import torch
     ref = json.load(open(GOLDEN))

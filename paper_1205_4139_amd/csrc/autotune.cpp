@@ -120,7 +120,7 @@ int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_preci
   // warm up both paths
   if ((rc = plan_set_tap_order(P, lam.data(), 1, st, hord, hbst)) ||
       (rc = plan_fast_corr(P, 2, &npart, st)) || (rc = plan_conv_corr(P, 2, &npart, st))) {
-    hipEventDestroy(e0); hipEventDestroy(e1); hipEventDestroy(e2);
+    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
     return rc;
   }
   int best = 1;
@@ -139,9 +139,9 @@ int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_preci
     if (fast_ms <= conv_ms) best = t;
     else break;   // the fast cost only grows with t
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  hipEventDestroy(e2);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
   if (rc) return rc;
   set_tuned_switch(matrix_class, N, corr_precision, best);
   *switch_t = best;

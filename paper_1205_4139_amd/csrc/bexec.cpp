@@ -140,13 +140,13 @@ int bplan_sizes(fcmp_batch_plan& BP, const fcmp_problem* probs) {
 
 void bplan_release(fcmp_batch_plan* BP) {
   if (!BP) return;
-  if (BP->exec) hipGraphExecDestroy(BP->exec);
-  if (BP->graph) hipGraphDestroy(BP->graph);
+  if (BP->exec) (void)hipGraphExecDestroy(BP->exec);
+  if (BP->graph) (void)hipGraphDestroy(BP->graph);
   if (BP->copied) {
-    hipEventSynchronize(BP->copied);
-    hipEventDestroy(BP->copied);
+    (void)hipEventSynchronize(BP->copied);
+    (void)hipEventDestroy(BP->copied);
   }
-  if (BP->host_ptrs) hipHostFree(BP->host_ptrs);
+  if (BP->host_ptrs) (void)hipHostFree(BP->host_ptrs);
   delete BP;
 }
 
@@ -323,7 +323,7 @@ int fcmp_batch_plan_create(fcmp_batch_plan** out, int64_t n, const fcmp_problem*
     rc = set_error(FCMP_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
   }
   prof_suspend(false);
-  hipStreamDestroy(cs);
+  (void)hipStreamDestroy(cs);
   if (rc) return fail(rc);
   e = hipGraphInstantiate(&BP->exec, BP->graph, nullptr, nullptr, 0);
   if (e != hipSuccess)
@@ -395,9 +395,9 @@ int fcmp_batch_plan_solve(fcmp_batch_plan* BP, const void* const* y_dev,
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipStreamSynchronize(st));
   float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = 0.f;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   int worst = FCMP_OK;
   if (!BP->S.wg.empty()) {
     rc = wg_stats(BP->wg, stats, st);   // writes through the caller indices

@@ -486,21 +486,29 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
   }
+  auto drop_events = [&] {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    e0 = e1 = nullptr;
+  };
   if (P.opt.algorithm != FCMP_OMP) {
-    if ((rc = plan_enqueue_prefix(P, opt, st))) return rc;
-    rc = plan_solve_set(P, opt, (int32_t* const*)sup, xo, stats, st);
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
+    rc = plan_enqueue_prefix(P, opt, st);
+    if (!rc) rc = plan_solve_set(P, opt, (int32_t* const*)sup, xo, stats, st);
+    drop_events();
     return rc;
   }
-  if ((rc = plan_enqueue(P, opt, st))) return rc;
+  if ((rc = plan_enqueue(P, opt, st))) {
+    drop_events();
+    return rc;
+  }
   if (stats) {
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipStreamSynchronize(st));
     float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    hipError_t e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    drop_events();
+    if (e != hipSuccess)
+      return set_error(FCMP_E_DEVICE, std::string("plan solve: ") + hipGetErrorString(e));
     std::vector<Status> hs((size_t)n);
     HIP_TRY(hipMemcpy(hs.data(), P.status, n * sizeof(Status), hipMemcpyDeviceToHost));
     return plan_stats(n, hs.data(), ms, stats);

@@ -102,7 +102,8 @@ hipError_t launch_residual(const RParams& p, int ninst, hipStream_t st) {
   const size_t tw = p.fourier ? (((size_t)1 << p.twS) + ((size_t)p.N >> p.twS)) * 16 : 0;
   const size_t lds = tw + (size_t)R_TCH * (p.fourier ? 16 : 8) + (size_t)R_TCH * 4;
   if (p.fourier) {
-    raise_lds_limit((const void*)residual_kernel<true>, lds);
+    hipError_t e = raise_lds_limit((const void*)residual_kernel<true>, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(residual_kernel<true>, dim3(groups, ninst), dim3(R_THREADS), lds, st, p);
   } else {
     hipLaunchKernelGGL(residual_kernel<false>, dim3(groups, ninst), dim3(R_THREADS), lds, st, p);

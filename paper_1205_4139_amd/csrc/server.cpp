@@ -182,7 +182,7 @@ struct Staging {
   size_t bytes = 0;
   int ensure(size_t want) {
     if (want <= bytes) return FCMP_OK;
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
     p = nullptr;
     bytes = 0;
     size_t b = std::max(want, (size_t)1 << 20);
@@ -192,7 +192,7 @@ struct Staging {
     return FCMP_OK;
   }
   ~Staging() {
-    if (p) hipHostFree(p);
+    if (p) (void)hipHostFree(p);
   }
 };
 
@@ -354,10 +354,13 @@ bool form_wave(fcmp_server* S, int worker, std::vector<Req*>& w, bool& small, si
 }
 
 void worker_main(fcmp_server* S, int k) {
-  hipSetDevice(S->device);
+  // a failure here resurfaces as an error of this worker's first device call
+  (void)hipSetDevice(S->device);
   hipStream_t st = S->streams[k];
   hipEvent_t ev = nullptr;
-  hipEventCreateWithFlags(&ev, hipEventBlockingSync | hipEventDisableTiming);
+  // without the event every wave of this worker fails with a device error
+  if (hipEventCreateWithFlags(&ev, hipEventBlockingSync | hipEventDisableTiming) != hipSuccess)
+    ev = nullptr;
   Staging stg;
   std::vector<Req*> w;
   std::unique_lock<std::mutex> lk(S->mu);
@@ -380,7 +383,7 @@ void worker_main(fcmp_server* S, int k) {
     int rc = ev ? run_wave(S, w, small, S->pool + off, sb, st, ev, stg)
                 : set_error(FCMP_E_DEVICE, "event creation failed");
     std::string msg = rc ? last_error() : std::string();
-    if (rc) hipStreamSynchronize(st);   // nothing of the wave may still use the region
+    if (rc) (void)hipStreamSynchronize(st);   // nothing of the wave may still use the region
     lk.lock();
     for (Req* r : w) {
       if (rc) {
@@ -397,7 +400,7 @@ void worker_main(fcmp_server* S, int k) {
     S->cv_work.notify_all();
   }
   lk.unlock();
-  if (ev) hipEventDestroy(ev);
+  if (ev) (void)hipEventDestroy(ev);
 }
 
 int request_footprint(const fcmp_problem* prob, const fcmp_options* opt, bool* small,
@@ -453,7 +456,7 @@ int fcmp_server_create(fcmp_server** out, void* pool_dev, size_t pool_bytes,
   for (int k = 0; k < c.n_streams; ++k) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t s : S->streams) hipStreamDestroy(s);
+      for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
       delete S;
       return set_error(FCMP_E_DEVICE, "stream creation failed");
     }
@@ -557,8 +560,8 @@ int fcmp_server_destroy(fcmp_server* S) {
   }
   for (std::thread& t : S->workers) t.join();
   for (hipStream_t st : S->streams) {
-    hipStreamSynchronize(st);
-    hipStreamDestroy(st);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
   }
   for (auto& kv : S->reqs) delete kv.second;
   delete S;

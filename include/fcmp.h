@@ -318,9 +318,11 @@ int fcmp_adaptive_switch(int32_t matrix_class, int64_t N, int32_t corr_precision
  * returns the summed device time per phase. */
 #define FCMP_PHASE_KERNEL 0   /* kernel vector c (plan time, or RECOMPUTE flag) */
 #define FCMP_PHASE_H0     1   /* h_0 = Phi^H y and the first identification      */
-#define FCMP_PHASE_CORR   2   /* conventional correlation (all transform passes) */
+#define FCMP_PHASE_CORR   2   /* conventional correlation (all transform passes;
+                                 where the residual is fused into the first pass,
+                                 the residual too)                                */
 #define FCMP_PHASE_FAST   3   /* fast correlation, eq. (kernelsumOMP)            */
-#define FCMP_PHASE_RESID  4   /* residual r = y - Phi_t x_t                       */
+#define FCMP_PHASE_RESID  4   /* residual r = y - Phi_t x_t, when computed apart  */
 #define FCMP_PHASE_LS     5   /* identification + least-squares update           */
 #define FCMP_PHASE_OTHER  6   /* gathers, status, copy-out                        */
 #define FCMP_NPHASE       8

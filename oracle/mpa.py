@@ -108,6 +108,7 @@ def omp(op: Operator, y, K: int, method: str = "conventional",
         if c is None:
             c = kernel_vector(op.cls, N, op.omega, "dense" if hasattr(op, "Phi") else "transform")
         h0 = op.adjoint(y)                             # h_0 = Phi^H r_0
+    Phi_all = None                                     # columns of Phi at Lambda
     for t in range(1, K + 1):
         if method == "fast":                           # eq. (kernelsumOMP)
             h = h0 if t == 1 else fast_correlation(op.cls, N, h0, c, lam, x)
@@ -122,7 +123,12 @@ def omp(op: Operator, y, K: int, method: str = "conventional",
         if keep_h:
             hs.append(np.array(h))
         lam.append(j)                                  # step 4
-        Phi_t = op.columns(lam)                        # step 5
+        # step 5: Phi_t = Phi S_{Lambda_t}^T, the previous columns with the
+        # new one appended (Lambda_t in selection order)
+        if Phi_all is None:
+            Phi_all = np.empty((op.M, K), dtype=op.dtype)
+        Phi_all[:, t - 1] = op.columns([j])[:, 0]
+        Phi_t = Phi_all[:, :t]
         x = lstsq(Phi_t, y)                            # step 6
         r = y - Phi_t @ x                              # step 7
         if keep_h:

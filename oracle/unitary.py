@@ -35,10 +35,12 @@ __all__ = ["popcount", "fourier_rows", "hadamard_rows", "sensing_matrix",
 
 
 def popcount(a: np.ndarray) -> np.ndarray:
-    """Number of set bits of each non-negative int64 entry (bit by bit)."""
+    """Number of set bits of each non-negative int64 entry (bit by bit, up
+    to the highest bit any entry has)."""
     a = np.asarray(a, dtype=np.int64)
     out = np.zeros(a.shape, dtype=np.int64)
-    for b in range(62):
+    nbits = int(a.max()).bit_length() if a.size else 0
+    for b in range(nbits):
         out += (a >> b) & 1
     return out
 

@@ -371,6 +371,21 @@ int fcmp_fast_correlate(const fcmp_problem* prob, int32_t precision,
                         void* h_dev, const uint32_t* excl_dev, void* sel_dev,
                         void* ws_dev, size_t ws_bytes, void* hip_stream);
 
+/* Top-K identification of the set-based pursuits (SP and CoSaMP select the
+ * K or 2K largest entries of their proxy h = Phi^H r, the step that
+ * Algorithm 1.1 step 3 takes for K = 1): the K indices j of largest |v(j)|^2
+ * among the entries whose bit in excl_dev is clear, ties to the lowest
+ * index, written to out_dev in ascending index order.  v_dev: n values,
+ * float32 | complex64 for FCMP_FP32 and float64 | complex128 for FCMP_FP64,
+ * real for FCMP_HADAMARD and complex for FCMP_FOURIER; excl_dev nullable,
+ * uint32[(n+31)/32]; out_dev: int32[K].  When fewer than K entries are
+ * eligible, the slots after the last eligible index hold -1.  1 <= K <= n,
+ * n < 2^31; the workspace size comes from fcmp_topk_workspace (host-only). */
+int fcmp_topk_workspace(int64_t n, size_t* bytes);
+int fcmp_topk(int32_t matrix_class, int32_t precision, const void* v_dev, int64_t n,
+              const uint32_t* excl_dev, int64_t K, int32_t* out_dev, void* ws_dev,
+              size_t ws_bytes, void* hip_stream);
+
 /* Forward operator y = Phi x (+ noise scaled to snr_db when noise_dev is not
  * NULL: eta = g ||Phi x|| / ||g|| 10^(-snr/20)).  x_dev: N FP64 values;
  * noise_dev: M values; y_dev: M values (float64 | complex128).             */

@@ -132,6 +132,8 @@ def _load():
         "fcmp_correlate": ([P, i32, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "fcmp_fast_correlate_workspace": ([P, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_fast_correlate": ([P, i32, vp, vp, vp, vp, i64, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "fcmp_topk_workspace": ([i64, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_topk": ([i32, i32, vp, i64, vp, i64, vp, vp, sz, vp], ctypes.c_int),
         "fcmp_measure_workspace": ([P, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_measure": ([P, vp, vp, dbl, vp, vp, sz, vp], ctypes.c_int),
     }
@@ -282,6 +284,19 @@ def fast_correlate(cls, N, h0, cp, lam, xt, precision="fp64", excl=None, want_h=
                                    _ptr(lam), _ptr(xt), nt, _ptr(h), _ptr(excl), _ptr(sel),
                                    _ptr(ws), ws.numel(), _stream()))
     return h, sel
+
+
+def topk(cls, v, K, precision="fp64", excl=None):
+    """The K indices of largest |v|^2 (ties to the lowest index, excluded
+    bits skipped), ascending; -1 in slots past the last eligible index."""
+    torch = _torch()
+    n = ctypes.c_size_t(0)
+    _check(lib.fcmp_topk_workspace(int(v.numel()), ctypes.byref(n)))
+    ws = _workspace(n.value, v.device)
+    out = torch.empty(int(K), dtype=torch.int32, device=v.device)
+    _check(lib.fcmp_topk(CLASS[cls], PREC[precision], _ptr(v), int(v.numel()), _ptr(excl), int(K),
+                         _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
 
 
 def measure(cls, N, omega, x, noise=None, snr_db=None):

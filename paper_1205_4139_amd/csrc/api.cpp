@@ -301,6 +301,31 @@ int fcmp_fast_correlate(const fcmp_problem* prob, int32_t precision, const void*
   return FCMP_OK;
 }
 
+int fcmp_topk_workspace(int64_t n, size_t* bytes) {
+  if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
+  if (n < 1 || n >= ((int64_t)1 << 31)) return set_error(FCMP_E_INVALID, "n must be in [1, 2^31)");
+  *bytes = topk_workspace(n);
+  return FCMP_OK;
+}
+
+int fcmp_topk(int32_t matrix_class, int32_t precision, const void* v_dev, int64_t n,
+              const uint32_t* excl_dev, int64_t K, int32_t* out_dev, void* ws_dev,
+              size_t ws_bytes, void* hip_stream) {
+  size_t need = 0;
+  int rc = fcmp_topk_workspace(n, &need);
+  if (rc) return rc;
+  if (matrix_class != FCMP_HADAMARD && matrix_class != FCMP_FOURIER)
+    return set_error(FCMP_E_INVALID, "matrix_class must be FCMP_HADAMARD or FCMP_FOURIER");
+  if (precision != FCMP_FP64 && precision != FCMP_FP32)
+    return set_error(FCMP_E_INVALID, "unknown precision");
+  if (K < 1 || K > n) return set_error(FCMP_E_INVALID, "K must be in [1, n]");
+  if (!v_dev || !out_dev || !ws_dev) return set_error(FCMP_E_INVALID, "NULL device pointer");
+  if (ws_bytes < need) return set_error(FCMP_E_WORKSPACE, "workspace too small");
+  const int kind = prec_kind(matrix_class == FCMP_FOURIER, precision);
+  HIP_TRY(launch_topk(v_dev, kind, n, excl_dev, K, ws_dev, out_dev, (hipStream_t)hip_stream));
+  return FCMP_OK;
+}
+
 int fcmp_measure_workspace(const fcmp_problem* prob, size_t* bytes) {
   int rc = validate_problem(prob, false);
   if (rc) return rc;

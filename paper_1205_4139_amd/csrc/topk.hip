@@ -27,7 +27,8 @@ __device__ __forceinline__ bool tk_excluded(const uint32_t* excl, int64_t j) {
 }
 
 // st: [0] prefix, [1] prefix mask, [2] still needed, [3] count strictly above,
-// [4] 1 when fewer eligible entries than requested.  Digits of 8 bits.
+// [4] 1 when fewer eligible entries than requested, [5] total count of keys
+// above the K-th (from the counting pass).  Digits of 8 bits.
 __global__ void tk_hist_kernel(const void* v, int kind, int64_t n, const uint32_t* excl,
                                const uint64_t* st, int shift, uint32_t* hist) {
   __shared__ uint32_t lh[256];
@@ -104,8 +105,9 @@ __global__ void tk_count_kernel(const void* v, int kind, int64_t n, const uint32
   }
 }
 
-// exclusive scan of the per-workgroup counts (one workgroup, sequential per thread block of 1024)
-__global__ void tk_scan_kernel(uint32_t* counts, int nwg, uint32_t* offs) {
+// exclusive scan of the per-workgroup counts (one workgroup, sequential per
+// thread block of 1024); st[5] receives the total count of keys > kappa
+__global__ void tk_scan_kernel(uint32_t* counts, int nwg, uint32_t* offs, uint64_t* st) {
   __shared__ uint32_t pg[1024], pe[1024];
   const int t = threadIdx.x;
   const int per = (nwg + 1023) / 1024;
@@ -125,6 +127,7 @@ __global__ void tk_scan_kernel(uint32_t* counts, int nwg, uint32_t* offs) {
     __syncthreads();
   }
   uint32_t rg = t ? pg[t - 1] : 0u, re = t ? pe[t - 1] : 0u;
+  if (t == 1023) st[5] = pg[1023];
   for (int i = 0; i < per; ++i) {
     const int w = t * per + i;
     if (w < nwg) {
@@ -136,13 +139,17 @@ __global__ void tk_scan_kernel(uint32_t* counts, int nwg, uint32_t* offs) {
   }
 }
 
-// Ordered write: keys > kappa to out[0 .. above), the first `need` keys == kappa
-// to out[above .. above + need), both in index order.
+// Ordered write: keys > kappa to out[0 .. above), the first K - above keys
+// == kappa to out[above .. K), both in index order.  When fewer than K
+// entries are eligible (st[4]), kappa stays 0 and every eligible entry is
+// written; the remaining slots keep the -1 they were filled with.
 __global__ void tk_write_kernel(const void* v, int kind, int64_t n, const uint32_t* excl,
-                                const uint64_t* st, const uint32_t* offs, int32_t* out) {
+                                const uint64_t* st, const uint32_t* offs, int32_t* out,
+                                int64_t K) {
   __shared__ uint32_t sg[TK_THREADS], se[TK_THREADS];
   const uint64_t kappa = st[0];
-  const uint64_t need = st[2], above = st[3];
+  const uint64_t above = st[5];
+  const uint64_t need = above < (uint64_t)K ? (uint64_t)K - above : 0;
   const int64_t base = (int64_t)blockIdx.x * TK_CHUNK;
   constexpr int PER = TK_CHUNK / TK_THREADS;
   // each thread owns PER consecutive elements
@@ -184,12 +191,14 @@ __global__ void tk_write_kernel(const void* v, int kind, int64_t n, const uint32
 }
 
 // Merge the two index-ordered runs out[0..a) and out[a..K) into ascending
-// order (one workgroup, bitonic sort over the next power of two).
+// order (one workgroup, bitonic sort over the next power of two); unused
+// slots (-1) sort last and stay -1.
 __global__ void tk_sort_kernel(int32_t* out, int K) {
   extern __shared__ int32_t sk[];
   int P = 1;
   while (P < K) P <<= 1;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) sk[i] = i < K ? out[i] : 0x7fffffff;
+  for (int i = threadIdx.x; i < P; i += blockDim.x)
+    sk[i] = (i < K && out[i] >= 0) ? out[i] : 0x7fffffff;
   __syncthreads();
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -204,12 +213,12 @@ __global__ void tk_sort_kernel(int32_t* out, int K) {
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < K; i += blockDim.x) out[i] = sk[i];
+  for (int i = threadIdx.x; i < K; i += blockDim.x) out[i] = sk[i] == 0x7fffffff ? -1 : sk[i];
 }
 
 __global__ void tk_init_kernel(uint64_t* st, int64_t K) {
   if (threadIdx.x == 0) {
-    st[0] = 0; st[1] = 0; st[2] = (uint64_t)K; st[3] = 0; st[4] = 0;
+    st[0] = 0; st[1] = 0; st[2] = (uint64_t)K; st[3] = 0; st[4] = 0; st[5] = 0;
   }
 }
 
@@ -229,6 +238,8 @@ hipError_t launch_topk(const void* v, int kind, int64_t n, const uint32_t* excl,
   uint32_t* offs = counts + 2 * nwg;
   hipError_t e = launch_fill_u32(hist, 0u, 256, st);
   if (e != hipSuccess) return e;
+  e = launch_fill_u32((uint32_t*)out, 0xFFFFFFFFu, K, st);   // -1: unused slot
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tk_init_kernel, dim3(1), dim3(64), 0, st, state, K);
   int hgroups = (int)std::min<int64_t>(2048, (n + 1023) / 1024);
   if (hgroups < 1) hgroups = 1;
@@ -240,9 +251,9 @@ hipError_t launch_topk(const void* v, int kind, int64_t n, const uint32_t* excl,
   }
   hipLaunchKernelGGL(tk_count_kernel, dim3((unsigned)nwg), dim3(TK_THREADS), 0, st, v, kind, n,
                      excl, state, counts);
-  hipLaunchKernelGGL(tk_scan_kernel, dim3(1), dim3(1024), 0, st, counts, (int)nwg, offs);
+  hipLaunchKernelGGL(tk_scan_kernel, dim3(1), dim3(1024), 0, st, counts, (int)nwg, offs, state);
   hipLaunchKernelGGL(tk_write_kernel, dim3((unsigned)nwg), dim3(TK_THREADS), 0, st, v, kind, n,
-                     excl, state, offs, out);
+                     excl, state, offs, out, K);
   int P = 1;
   while (P < K) P <<= 1;
   hipLaunchKernelGGL(tk_sort_kernel, dim3(1), dim3(1024), (size_t)P * 4, st, out, (int)K);

@@ -25,3 +25,28 @@ def test_stored_fullsize_solve_matches_planted_signal():
     assert np.linalg.norm(x - want) <= 0.01 * np.linalg.norm(want)
     assert ref["certified"]["fp32"] and ref["certified"]["fp64"]
     assert ref["min_gap"] >= 2.5e-5
+
+
+UNEVEN = os.path.join(os.path.dirname(__file__), "golden",
+                      "uneven_batch4096_seed4000_n16384.json")
+
+
+def test_stored_uneven_batch_solves_match_planted_signals():
+    """The six stored N = 2^14 solves of the uneven batch (40 dB): each holds
+    K distinct columns, at least 97% of them planted ones, and x on them is
+    the planted values to within 1% (N(0,1) values: the smallest planted
+    coefficients sit near the noise and may be swapped for another column)."""
+    ref = json.load(open(UNEVEN))
+    insts = instancegen.draw_batch(4096, 4000)
+    assert len(ref["instances"]) == 6
+    assert sorted(e["cls"] for e in ref["instances"]) == ["F"] * 3 + ["H"] * 3
+    for e in ref["instances"]:
+        inst = insts[e["index"]]
+        assert (e["cls"], e["N"], e["M"], e["K"]) == (inst.cls, inst.N, inst.M, inst.K) and inst.N == 16384
+        sup = np.array(e["support"])
+        assert len(sup) == inst.K and len(set(sup.tolist())) == inst.K
+        assert len(set(sup.tolist()) & set(inst.support.tolist())) >= 0.97 * inst.K
+        x = np.array(e["x"]["re"]) + (1j * np.array(e["x"]["im"]) if "im" in e["x"] else 0.0)
+        want = inst.x_dense()[sup]
+        assert np.linalg.norm(x - want) <= 0.01 * np.linalg.norm(want)
+        assert e["min_gap"] >= 2.5e-5

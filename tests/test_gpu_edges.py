@@ -75,6 +75,8 @@ def test_omp_degenerate_shapes(fc, case, method, precision):
     res = fc.solve(cls, N, M, K, inst.omega, to_dev(y), method=method, precision=precision)
     assert res.stats.status == 0
     assert res.stats.iterations == K
-    if certify.certified(ref, precision):
-        assert list(to_np(res.support)) == list(ref.support)
-        assert np.linalg.norm(to_np(res.x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    # every case's seed was chosen so the oracle's gaps certify it at both
+    # precisions (smallest gap 2.9e-3 over the list), so each one is checked
+    assert certify.certified(ref, precision)
+    assert list(to_np(res.support)) == list(ref.support)
+    assert np.linalg.norm(to_np(res.x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)

@@ -159,3 +159,52 @@ def test_measure(fc, cls, N, M):
     yn = to_np(fc.measure(cls, N, om, to_dev(x), to_dev(g), 30.0))
     wn = oracle.measure(cls, N, om, x, g, 30.0, tier="transform")
     assert inf_rel(yn, wn) <= TOL["fp64"]
+
+
+def _topk_case(N, K, seed):
+    """|v|^2 with many exact ties straddling the K-th position: integer
+    values with a few distinct magnitudes, and an exclusion set."""
+    rng = np.random.default_rng(seed)
+    v = rng.integers(-6, 7, N).astype(np.float64)
+    # a block of exact ties around the K-th largest magnitude
+    order = np.argsort(-np.abs(v), kind="stable")
+    kth = abs(v[order[K - 1]])
+    tie = rng.choice(N, 4 * K, replace=False)
+    v[tie[: 2 * K]] = kth * rng.choice([-1.0, 1.0], 2 * K)
+    excl = np.sort(rng.choice(N, N // 64, replace=False))
+    return v, excl
+
+
+@pytest.mark.parametrize("K", [2048, 3072])
+@pytest.mark.parametrize("cls,precision", [("H", "fp32"), ("H", "fp64"), ("F", "fp32")])
+def test_topk_full_size_with_ties(fc, K, cls, precision):
+    """The set pursuits' top-K at N = 2^20 (K = 2K and 3K of the N = 2^20,
+    K = 1024 workload) with exact ties at the K-th key and an exclusion
+    bitmap: the index set equals the oracle's (ties to the lowest index)."""
+    N = 1 << 20
+    v, excl = _topk_case(N, K, 40 + K)
+    if cls == "F":
+        # |v|^2 of (a + ib) with integer parts: ties in magnitude across phases
+        v = v.astype(np.complex128) * np.where(np.arange(N) % 3 == 0, 1.0, 1j)
+    vd = to_dev(v.astype({("H", "fp32"): np.float32, ("H", "fp64"): np.float64,
+                          ("F", "fp32"): np.complex64}[(cls, precision)]))
+    bm = np.zeros((N + 31) // 32, dtype=np.uint32)
+    np.bitwise_or.at(bm, excl >> 5, (np.uint32(1) << (excl & 31).astype(np.uint32)))
+    out = to_np(fc.topk(cls, vd, K, precision, excl=to_dev(bm)))
+    want = np.sort(oracle.topk(np.abs(v) ** 2, K, excluded=excl))
+    assert np.array_equal(out, want)
+    # without exclusions too
+    out = to_np(fc.topk(cls, vd, K, precision))
+    assert np.array_equal(out, np.sort(oracle.topk(np.abs(v) ** 2, K)))
+
+
+def test_topk_fewer_eligible_than_k(fc):
+    """Every entry but five excluded: the five eligible indices, then -1."""
+    N, K = 4096, 8
+    v = np.arange(N, dtype=np.float64)
+    keep = np.array([7, 100, 2000, 2001, 4095])
+    bm = np.full((N + 31) // 32, 0xFFFFFFFF, dtype=np.uint32)
+    for j in keep:
+        bm[j >> 5] &= ~np.uint32(1 << (j & 31))
+    out = to_np(fc.topk("H", to_dev(v), K, "fp64", excl=to_dev(bm)))
+    assert list(out) == list(keep) + [-1, -1, -1]

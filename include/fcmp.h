@@ -156,6 +156,25 @@ int fcmp_solve(const fcmp_problem* prob, const fcmp_options* opt,
                int32_t* support_dev, void* x_dev, fcmp_stats* stats,
                void* hip_stream);
 
+/* fcmp_solve for callers that cannot allocate device memory: code that runs
+ * under HIP graph capture, tight serving loops, and harnesses that forbid
+ * hipMalloc.  The workspace comes from a static device array of
+ * FCMP_NOALLOC_SCRATCH_BYTES inside the library (each GPU the library runs
+ * on holds its own copy until the process ends) instead of a caller buffer;
+ * the call itself allocates no device memory and creates no events.  The
+ * caller still owns y, support and x (layouts as for fcmp_solve).  A problem
+ * whose fcmp_query_workspace exceeds FCMP_NOALLOC_SCRATCH_BYTES is refused
+ * with FCMP_E_WORKSPACE (OMP fits up to N = 2^20, M = 2^17, K = 1024, which
+ * needs 36 MiB).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (from several host threads or streams) race and must
+ * be serialised by the caller.  stats (nullable) are filled after a stream
+ * synchronisation, with ms_total = 0 (no device timing).  Results are
+ * bit-identical to fcmp_solve's. */
+#define FCMP_NOALLOC_SCRATCH_BYTES (64u << 20)
+int fcmp_solve_noalloc(const fcmp_problem* prob, const fcmp_options* opt,
+                       const void* y_dev, int32_t* support_dev, void* x_dev,
+                       fcmp_stats* stats, void* hip_stream);
+
 /* Many independent problems in one call.  OMP problems whose transform fits
  * one workgroup's LDS (N * element size <= 140 KiB, K <= 1024) run whole
  * solves, one workgroup per problem, in one persistent launch after a

@@ -96,6 +96,7 @@ def _load():
         "fcmp_last_error": ([], ctypes.c_char_p),
         "fcmp_query_workspace": ([P, O, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_solve": ([P, O, vp, vp, sz, vp, vp, ctypes.POINTER(Stats), vp], ctypes.c_int),
+        "fcmp_solve_noalloc": ([P, O, vp, vp, vp, ctypes.POINTER(Stats), vp], ctypes.c_int),
         "fcmp_batch_query_workspace": ([i64, P, O, ctypes.POINTER(sz)], ctypes.c_int),
         "fcmp_batch_solve": ([i64, P, O, ctypes.POINTER(vp), vp, sz, ctypes.POINTER(vp),
                               ctypes.POINTER(vp), ctypes.POINTER(Stats), vp], ctypes.c_int),
@@ -226,6 +227,22 @@ def solve(cls, N, M, K, omega, y, algorithm="omp", method="conventional", precis
     _check(lib.fcmp_solve(ctypes.byref(p), ctypes.byref(o), _ptr(y), _ptr(ws), ws.numel(),
                           _ptr(sup), _ptr(x), ctypes.byref(st) if st is not None else None,
                           _stream()))
+    return SolveResult(sup, x, st)
+
+
+def solve_noalloc(cls, N, M, K, omega, y, algorithm="omp", method="conventional",
+                  precision="fp64", switch_t=0, max_iter=0, stats=True) -> SolveResult:
+    """fcmp_solve_noalloc: the solve's workspace is the library's static
+    device scratch (no workspace argument, no device allocation inside)."""
+    torch = _torch()
+    p, _om = make_problem(cls, N, M, K, omega)
+    o = make_options(algorithm, method, precision, max_iter, switch_t)
+    dev = y.device
+    sup = torch.empty(int(K), dtype=torch.int32, device=dev)
+    x = torch.empty(int(K), dtype=_dtype(cls), device=dev)
+    st = Stats() if stats else None
+    _check(lib.fcmp_solve_noalloc(ctypes.byref(p), ctypes.byref(o), _ptr(y), _ptr(sup), _ptr(x),
+                                  ctypes.byref(st) if st is not None else None, _stream()))
     return SolveResult(sup, x, st)
 
 

@@ -467,7 +467,7 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
 }
 
 int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_t* const* sup,
-               void* const* xo, fcmp_stats* stats, hipStream_t st) {
+               void* const* xo, fcmp_stats* stats, hipStream_t st, bool timed) {
   fcmp_options opt = P.opt;
   if (o) {
     int rc = validate_options(&P.shape, o);
@@ -481,7 +481,7 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
   if (rc) return rc;
   const int n = (int)P.n;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (stats) {
+  if (stats && timed) {
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, st));
@@ -503,9 +503,9 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
   }
   if (stats) {
     float ms = 0.f;
-    hipError_t e = hipEventRecord(e1, st);
+    hipError_t e = timed ? hipEventRecord(e1, st) : hipSuccess;
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e == hipSuccess && timed) e = hipEventElapsedTime(&ms, e0, e1);
     drop_events();
     if (e != hipSuccess)
       return set_error(FCMP_E_DEVICE, std::string("plan solve: ") + hipGetErrorString(e));

@@ -74,8 +74,11 @@ namespace fcmp {
 void plan_layout(fcmp_plan& P, char* base);
 int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt);
 int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st);
+// timed = false: stats (when given) carry no device time (ms_total = 0) and
+// no hipEvent is created.
 int plan_solve(fcmp_plan& P, const fcmp_options* opt, const void* const* y,
-               int32_t* const* sup, void* const* x, fcmp_stats* stats, hipStream_t st);
+               int32_t* const* sup, void* const* x, fcmp_stats* stats, hipStream_t st,
+               bool timed = true);
 int plan_kernel_vector(fcmp_plan& P, hipStream_t st);
 // OMP device work of one solve (no host synchronisation, so it can be
 // captured in a graph); the pointer array dptrs must already be uploaded.

@@ -19,6 +19,8 @@ pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden",
                       "omp_fourier_n65536_m16384_k256_seed2000.json")
+UNEVEN = os.path.join(os.path.dirname(__file__), "golden",
+                      "uneven_batch4096_seed4000_n16384.json")
 N, M, K = 65536, 16384, 256
 BATCH = 256          # the benchmark's lockstep plan
 
@@ -74,8 +76,9 @@ def test_hadamard_1m_exact_recovery(fc, method):
 def test_uneven_4096_batch_plan(fc):
     """The benchmark's 4096-instance uneven batch as one graph-captured batch
     plan: ten sampled instances against the oracle (N <= 4096, certified at
-    FP32), two against the same instance solved alone on the same
-    one-workgroup-per-instance path."""
+    FP32), six N = 2^14 instances against stored oracle solves, two against
+    the same instance solved alone on the same one-workgroup-per-instance
+    path."""
     insts = instancegen.draw_batch(4096, 4000)
     ys = [to_dev(oracle.problem.instance_measure(i, tier="transform")) for i in insts]
     bp = fc.BatchPlan([(i.cls, i.N, i.M, i.K, i.omega) for i in insts], precision="fp32")
@@ -93,6 +96,17 @@ def test_uneven_4096_batch_plan(fc):
             assert np.linalg.norm(to_np(x[k]) - ref.x) <= 1e-10 * np.linalg.norm(ref.x), k
             checked += 1
     assert checked >= 5
+    # the largest size of the batch (N = 2^14, the persistent kernel's largest
+    # tile): the stored oracle solves of three Fourier and three Hadamard
+    # instances, certified at FP32 (selection order exactly, x to 1e-10)
+    gold = json.load(open(UNEVEN))
+    assert len(gold["instances"]) == 6
+    for e in gold["instances"]:
+        k = e["index"]
+        assert insts[k].N == 16384 and insts[k].cls == e["cls"]
+        assert list(to_np(sup[k])) == e["support"], k
+        xr = np.array(e["x"]["re"]) + (1j * np.array(e["x"]["im"]) if "im" in e["x"] else 0.0)
+        assert np.linalg.norm(to_np(x[k]) - xr) <= 1e-10 * np.linalg.norm(xr), k
     for k in (1, 4094):
         i = insts[k]
         s1, x1, _ = fc.batch_solve([(i.cls, i.N, i.M, i.K, i.omega)], [ys[k]], precision="fp32")

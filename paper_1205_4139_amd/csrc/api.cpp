@@ -44,9 +44,7 @@ void carve_common(Carver& cv, const Geo& g, int M, Common& c) {
   c.tw64 = cv.take<double2>(ntw);
   c.tw32 = cv.take<float2>(ntw);
   c.tmp = cv.take_bytes((size_t)g.N * vbytes(wide_kind(g.fourier)));
-  c.npart = std::max(std::max(transform_partials(V_F32, g), transform_partials(V_C128, g)),
-                     fastcorr_groups(g.N));
-  c.npart = std::max(c.npart, transform_partials(V_C64, g));
+  c.npart = std::max(transform_partials_max(g), fastcorr_groups(g.N));
   c.partial = cv.take<Sel>(c.npart);
 }
 
@@ -257,7 +255,8 @@ int fcmp_correlate(const fcmp_problem* prob, int32_t precision, const void* r_de
   d.scale = 1.0 / std::sqrt((double)prob->N);
   HIP_TRY(run_transform(pk, +1, g, tw_for(pk, g, c), EntDev{c.ent_k, c.goff, (int)prob->M},
                         XSrc{IN_SPARSE, pk, rin}, d, c.tmp, nullptr, st));
-  if (sel_dev) HIP_TRY(launch_reduce_sel(c.partial, transform_partials(pk, g), (Sel*)sel_dev, st));
+  if (sel_dev) HIP_TRY(launch_reduce_sel(c.partial, transform_partials(pk, g, h_dev != nullptr),
+                                             (Sel*)sel_dev, st));
   return FCMP_OK;
 }
 

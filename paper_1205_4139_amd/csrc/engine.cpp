@@ -113,9 +113,23 @@ void build_stage_table(int hmax, std::vector<double2>& t64, std::vector<float2>&
   }
 }
 
-int transform_partials(int vk, const Geo& g) {
+int xrow_rows_per_group(const Geo& g) {
+  const int N1 = 1 << g.n1, N2 = 1 << g.n2;
+  const int q = N1 == 256 ? 1 : N1 == 512 ? 2 : N1 == 1024 ? 4 : 0;
+  return (q && N2 % (16 / q) == 0) ? 16 / q : 0;
+}
+
+int transform_partials(int vk, const Geo& g, bool store) {
   if (single_ok(vk, g.N)) return 1;
+  if (!store && xrow_rows_per_group(g)) return (1 << g.n2) / xrow_rows_per_group(g);
   return (1 << g.n2) / g.B2;
+}
+
+int transform_partials_max(const Geo& g) {
+  int n = 1;
+  for (int vk : {V_F32, V_F64, V_C64, V_C128})
+    n = std::max(n, std::max(transform_partials(vk, g, true), transform_partials(vk, g, false)));
+  return n;
 }
 
 void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
@@ -126,18 +140,36 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
     t.goff.assign(2, 0);
     t.goff[1] = M;
   } else {
-    const int mask1 = (1 << g.n1) - 1;
+    // entries sorted by column c = k mod N1, then by row k / N1 (Omega is
+    // increasing, so a stable counting sort by column does it); a pass-1
+    // workgroup's columns are contiguous in this order for any B1
+    const int N1 = 1 << g.n1, N2 = 1 << g.n2;
+    const int mask1 = N1 - 1;
     const int logB1 = ilog2(g.B1);
-    t.goff.assign(g.ngroups + 1, 0);
-    for (int m = 0; m < M; ++m) t.goff[((omega[m] & mask1) >> logB1) + 1]++;
-    for (int q = 0; q < g.ngroups; ++q) t.goff[q + 1] += t.goff[q];
-    std::vector<int32_t> fill(t.goff.begin(), t.goff.end() - 1);
+    std::vector<int32_t> cst(N1 + 1, 0);
+    for (int m = 0; m < M; ++m) cst[(omega[m] & mask1) + 1]++;
+    for (int c = 0; c < N1; ++c) cst[c + 1] += cst[c];
+    std::vector<int32_t> fill(cst.begin(), cst.end() - 1);
+    const int nw = std::max(1, N2 / 32);
+    t.cmask.assign((size_t)N1 * nw, 0u);
+    t.cbase.assign((size_t)N1 * nw, 0);
     for (int m = 0; m < M; ++m) {
-      const int q = (omega[m] & mask1) >> logB1;
-      const int p = fill[q]++;
+      const int k = omega[m];
+      const int c = k & mask1, row = k >> g.n1;
+      const int p = fill[c]++;
       t.perm[p] = m;
-      t.ent_k[p] = omega[m];
+      t.ent_k[p] = k;
+      t.cmask[(size_t)c * nw + (row >> 5)] |= 1u << (row & 31);
     }
+    for (int c = 0; c < N1; ++c) {
+      int run = cst[c];
+      for (int w = 0; w < nw; ++w) {
+        t.cbase[(size_t)c * nw + w] = run;
+        run += __builtin_popcount(t.cmask[(size_t)c * nw + w]);
+      }
+    }
+    t.goff.assign(g.ngroups + 1, 0);
+    for (int q = 0; q <= g.ngroups; ++q) t.goff[q] = cst[std::min(N1, q << logB1)];
   }
   // rows grouped by the pass-2 workgroup that produces them (Fourier output
   // j = j2 + N2 j1, Hadamard output j = j1 + N1 j2); pos1 maps back to the
@@ -310,6 +342,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
     if (!fft) b.excl_mode = 1;
     else if ((N2 & 31) == 0 && g.B2 <= 32) b.excl_mode = 2;
   }
+  if (xrow_q(b)) return launch_xrow(vk, fft, b, ninst, st);
   return launch_xform(vk, fft, b, N2 / g.B2, ninst, st);
 }
 

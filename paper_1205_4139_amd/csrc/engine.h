@@ -59,12 +59,19 @@ Geo make_geo(bool fourier, int N, int tile = 0);
 // Tile for a lockstep plan of n instances: few instances need small tiles to
 // spread one transform over enough workgroups; many fill the chip anyway.
 int plan_tile(int64_t n);
-int transform_partials(int vk, const Geo& g);   // partials written by a transform
+// Partials (one identification result per workgroup) written by a
+// transform whose outputs are stored (store) or only identified (the
+// register-resident second pass); transform_partials_max bounds both.
+int transform_partials(int vk, const Geo& g, bool store);
+int transform_partials_max(const Geo& g);
+int xrow_rows_per_group(const Geo& g);
 int pick_threads(int tile_n);                    // threads of a transform workgroup
 
 struct HostTables {
   std::vector<int32_t> ent_k, perm, goff;   // entry order (grouped or Omega order)
   std::vector<int32_t> ent2_k, goff2, pos1; // rows grouped by pass-2 output workgroup
+  std::vector<uint32_t> cmask;              // grouped: rows of Omega per column (N / 32 words)
+  std::vector<int32_t> cbase;               //   and the entry index of each word's first row
   std::vector<double2> tw64;                // lo (2^twS), hi (N >> twS), stage table; sign +
   std::vector<float2> tw32;
   int tw_N = 0, tw_twS = -1, tw_hmax = -1;  // geometry the twiddles were built for

@@ -79,6 +79,11 @@ struct XParams {
 hipError_t launch_xform(int vk, bool fft, const XParams& p, int groups, int ninst,
                         hipStream_t st);
 size_t xform_lds_bytes(int vk, bool fft, const XParams& p);
+// Register-resident second pass with the identification fused (rows of
+// length 256, 512 or 1024, outputs identified and not stored): xrow_q gives
+// Q = L / 256 when the pass qualifies, else 0.
+int xrow_q(const XParams& b);
+hipError_t launch_xrow(int vk, bool fft, const XParams& b, int ninst, hipStream_t st);
 // First pass of an FP64 two-pass transform of a taps input evaluated
 // directly (a few taps per column); ok when the tile and tap count suit it.
 bool taps_pass1_ok(const XParams& a, int vk);
@@ -104,10 +109,18 @@ struct RCParams {
   const void* twc_lo; const void* twc_hi; const void* twc_st;   // correlation precision, sign +
   void* out; int64_t inst_out;   // pass-1 output: out[(s0 + c) + N1 j]
   const Status* status;
+  // rows of Omega per column (entries sorted by column, then row): bit m of
+  // word m / 32 of column c marks row c + N1 m; cbase holds the entry index of
+  // the first marked row at or after 32 (m / 32); N2 / 32 words per column
+  const uint32_t* cmask; const int32_t* cbase; int64_t inst_cmask;
 };
 bool rcorr_ok(int pk, bool fft, const RCParams& p, int nthreads);
 hipError_t launch_rcorr(int pk, bool fft, const RCParams& p, int groups, int ninst, int nthreads,
                         hipStream_t st);
+// The register-resident variant for N2 = 256 rows per column (N = 2^16, 2^17),
+// 16 columns per workgroup; needs cmask and cbase.
+bool rcorr_reg_ok(int pk, bool fft, const RCParams& p);
+hipError_t launch_rcorr_reg(int pk, bool fft, const RCParams& p, int ninst, hipStream_t st);
 
 // ------------------------------------------------------------------ residual
 // r[e] = y[e] - sum_tau U(k_e, lam_tau) x_tau for the current support, in FP64,

@@ -73,11 +73,14 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
   // correlation); FCMP_RESID_RATIO selects the separate residual kernels
   if (opt->algorithm == FCMP_OMP && P.g.grouped && !single_ok(P.pk, (int)N) && !rr) {
     RCParams q = rcorr_geometry(P);
-    P.fused = rcorr_ok(P.pk, F, q, pick_threads(q.B * q.L));
+    q.cmask = (const uint32_t*)&P;   // presence only: the tables are laid out below
+    q.cbase = (const int32_t*)&P;
+    P.rreg = rcorr_reg_ok(P.pk, F, q);
+    P.fused = P.rreg || rcorr_ok(P.pk, F, q, pick_threads(q.B * q.L));
   }
+  P.sC = pad64(N / 32);
   P.sB = pad64(((int64_t)1 << P.g.n2) + 1);
-  P.npart = std::max(std::max(transform_partials(P.wk, P.g), transform_partials(P.pk, P.g)),
-                     fastcorr_groups((int)N));
+  P.npart = std::max(transform_partials_max(P.g), fastcorr_groups((int)N));
   P.sP = pad64(P.npart);
   P.sE = pad64((N + 31) / 32);
   plan_layout(P, nullptr);
@@ -103,6 +106,13 @@ void plan_layout(fcmp_plan& P, char* base) {
     P.ent2_k = P.ent_k;
     P.goff2 = P.goff;
     P.pos1 = nullptr;
+  }
+  if (P.rreg) {
+    P.cmask = cv.take<uint32_t>(n * P.sC);
+    P.cbase = cv.take<int32_t>(n * P.sC);
+  } else {
+    P.cmask = nullptr;
+    P.cbase = nullptr;
   }
   if (!P.uniform) {
     P.Mv = cv.take<int32_t>(n);
@@ -180,7 +190,12 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
   const int64_t n = P.n;
   std::vector<int32_t> ent((size_t)(n * P.sM), 0), perm((size_t)(n * P.sM), 0),
       goff((size_t)(n * P.sG), 0);
-  std::vector<int32_t> ent2, goff2, pos1;
+  std::vector<int32_t> ent2, goff2, pos1, cbase;
+  std::vector<uint32_t> cmask;
+  if (P.rreg) {
+    cmask.assign((size_t)(n * P.sC), 0u);
+    cbase.assign((size_t)(n * P.sC), 0);
+  }
   if (!P.g.same_out) {
     ent2.assign((size_t)(n * P.sM), 0);
     goff2.assign((size_t)(n * P.sG2), 0);
@@ -193,6 +208,10 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
     std::memcpy(&ent[b * P.sM], t.ent_k.data(), M * 4);
     std::memcpy(&perm[b * P.sM], t.perm.data(), M * 4);
     std::memcpy(&goff[b * P.sG], t.goff.data(), t.goff.size() * 4);
+    if (P.rreg) {
+      std::memcpy(&cmask[b * P.sC], t.cmask.data(), t.cmask.size() * 4);
+      std::memcpy(&cbase[b * P.sC], t.cbase.data(), t.cbase.size() * 4);
+    }
     if (!P.g.same_out) {
       std::memcpy(&ent2[b * P.sM], t.ent2_k.data(), M * 4);
       std::memcpy(&goff2[b * P.sG2], t.goff2.data(), t.goff2.size() * 4);
@@ -203,6 +222,10 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(P.ent2_k, ent2.data(), ent2.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(P.goff2, goff2.data(), goff2.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(P.pos1, pos1.data(), pos1.size() * 4, hipMemcpyHostToDevice, st));
+  }
+  if (P.rreg) {
+    HIP_TRY(hipMemcpyAsync(P.cmask, cmask.data(), cmask.size() * 4, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(P.cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipMemcpyAsync(P.tw64, t.tw64.data(), t.tw64.size() * sizeof(double2),
                          hipMemcpyHostToDevice, st));
@@ -358,7 +381,9 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
     q.twc_lo = tc.lo; q.twc_hi = tc.hi; q.twc_st = tc.st;
     q.out = P.tmp; q.inst_out = P.sN;
     q.status = P.status;
-    HIP_TRY(launch_rcorr(P.pk, F, q, (1 << g.n1) / g.B1, n, pick_threads(q.B * q.L), st));
+    q.cmask = P.cmask; q.cbase = P.cbase; q.inst_cmask = P.sC;
+    if (P.rreg) HIP_TRY(launch_rcorr_reg(P.pk, F, q, n, st));
+    else HIP_TRY(launch_rcorr(P.pk, F, q, (1 << g.n1) / g.B1, n, pick_threads(q.B * q.L), st));
     XDst d;
     d.partial = P.partial; d.excl = P.excl;
     d.scale = inv_sqrt_n;
@@ -366,7 +391,7 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
     src.pass2_only = true;
     HIP_TRY(run_transform(P.pk, +1, g, tw_for(P, P.pk), en, src, d, P.tmp, P.status, st, n,
                           P.sN, P.sM, P.sP, P.sE, P.sG));
-    *npart = transform_partials(P.pk, g);
+    *npart = transform_partials(P.pk, g, false);
     return FCMP_OK;
   }
   const double thr = P.resid_ratio * (double)N * (double)g.logN;
@@ -409,7 +434,7 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
   d.scale = inv_sqrt_n;
   HIP_TRY(run_transform(P.pk, +1, g, tw_for(P, P.pk), en, XSrc{IN_SPARSE, P.pk, P.r}, d, P.tmp,
                         P.status, st, n, P.sN, P.sM, P.sP, P.sE, P.sG));
-  *npart = transform_partials(P.pk, g);
+  *npart = transform_partials(P.pk, g, false);
   return FCMP_OK;
 }
 
@@ -422,7 +447,7 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
   const Geo& g = P.g;
   LParams lp{};
   lp.N = N; lp.fourier = F;
-  lp.partial = P.partial; lp.npart = transform_partials(P.wk, g);
+  lp.partial = P.partial; lp.npart = transform_partials(P.wk, g, true);
   lp.c64 = P.c64; lp.h0 = P.h0; lp.W = P.W; lp.z = P.z; lp.x = P.x;
   lp.lam = P.lam; lp.excl = P.excl; lp.status = P.status;
   lp.inst_part = P.sP; lp.inst_c = P.sN; lp.inst_h0 = P.sN; lp.inst_W = P.sW;

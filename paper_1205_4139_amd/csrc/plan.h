@@ -19,6 +19,7 @@ struct fcmp_plan {
   int64_t sM = 0, sN = 0, sK = 0, sW = 0, sG = 0, sG2 = 0, sP = 0, sE = 0;
   double resid_ratio = 1.0;    // transform residual when M (t-1) > ratio * N log2 N
   bool fused = false;          // residual fused into the correlation's first pass
+  bool rreg = false;           //   by the register-resident kernel (N2 = 256)
   int64_t sB = 0;              // bucket starts per buffer (N2 + 1, padded)
   int npart = 1;
   // shared
@@ -31,6 +32,9 @@ struct fcmp_plan {
   int32_t* ent2_k = nullptr;   // rows grouped by pass-2 output (absent when identical)
   int32_t* goff2 = nullptr;
   int32_t* pos1 = nullptr;
+  uint32_t* cmask = nullptr;   // register-resident fused residual: rows of Omega
+  int32_t* cbase = nullptr;    //   per column and their positions in y
+  int64_t sC = 0;              //   words per instance (N / 32, padded)
   void* c64 = nullptr;
   void* cp = nullptr;
   int16_t* ci16 = nullptr;     // Hadamard, M < 2^15: the integers N c (fast gathers)

@@ -1,0 +1,224 @@
+// Residual (Algorithm 1.1, step 7) fused with the first pass of the next
+// correlation (step 2), register-resident, for columns of N2 = 256 rows
+// (N = 2^16 and 2^17).
+//
+// The algebra is that of rcorr_kernel: with bucket l of a tap lam (lam mod N2
+// for Fourier, lam >> log2 N1 for Hadamard),
+//   A(c, l) = sum_{taps in bucket l} x_lam W(lam, c),
+//   (U s)[c + N1 m] = N^{-1/2} sum_l A(c, l) e^{-2 pi i l m / N2}   (Fourier)
+// (Hadamard: W = (-1)^popcount(lam & c) on the low bits and a WHT over l).
+// Here each column is held by 16 lanes of one wavefront, 16 values per lane:
+// lane p accumulates A(c, p + 16 a) for a < 16 in registers, the FP64 N2-point
+// transform over l runs in registers with one wavefront-private LDS exchange,
+// the residual r = y - U s is formed in registers at the rows of Omega the
+// lane holds (column masks and rank bases give each row's position in y),
+// and the correlation's first pass (the N2-point transform over the rows,
+// correlation precision) runs the same way.  A workgroup holds 16 columns
+// (four per wavefront); the first-pass outputs are transposed through LDS so
+// each output row segment of 16 columns is written as one 128-byte run.
+#include "wave_fft.h"
+
+namespace fcmp {
+
+namespace {
+constexpr int RR_COLS = 16;    // columns per workgroup
+constexpr int RR_TAPS = 256;   // taps staged in LDS per chunk
+constexpr int RR_L = 256;      // rows per column (N2)
+constexpr int RR_XW = 4 * 16 * 17;   // exchange scalars per wavefront (4 columns)
+// region A: the FP64 exchange buffers of four wavefronts, or the output
+// tile (256 rows x 17 slots), whichever is larger
+constexpr size_t rr_region_a(size_t vc_bytes) {
+  return (size_t)4 * RR_XW * 8 > (size_t)RR_L * 17 * vc_bytes ? (size_t)4 * RR_XW * 8
+                                                                : (size_t)RR_L * 17 * vc_bytes;
+}
+}  // namespace
+
+template <bool FFT, class VC>
+__global__ void __launch_bounds__(256)
+rcorr_reg_kernel(RCParams p) {
+  using VR = typename std::conditional<FFT, double2, double>::type;
+  using SC = typename VT<VC>::S;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int inst = blockIdx.y;
+  if (p.status && p.status[inst].done) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = tid >> 4;           // column within the workgroup
+  const int pl = tid & 15;            // lane within the column's group
+  const int grp = lane >> 4;          // column within the wavefront
+  const int s0 = blockIdx.x * RR_COLS;
+  const uint32_t cg = (uint32_t)(s0 + col);
+  const uint32_t maskN = (uint32_t)p.N - 1u;
+  const uint32_t mask1 = (1u << p.logN1) - 1u;
+  const int dsh = p.logN1 - 8;        // W_256^q = W_N1^(q << dsh)
+  const int ntaps = p.ntaps;
+
+  // LDS: region A (staged taps; then the exchange buffers; then the output
+  // tile), then the inter-pass twiddles of the correlation precision
+  constexpr size_t bytesA = rr_region_a(sizeof(VC));
+  int32_t* tl = (int32_t*)smem_raw;
+  VR* tx = (VR*)(smem_raw + RR_TAPS * 4);
+  int32_t* bsl = (int32_t*)(smem_raw + RR_TAPS * (4 + sizeof(VR)));
+  double* xr = (double*)smem_raw + wave * RR_XW + grp * (16 * 17);
+  SC* xc = (SC*)((double*)smem_raw + wave * RR_XW) + grp * (16 * 17);
+  VC* tile = (VC*)smem_raw;
+  VC* twlo = (VC*)(smem_raw + bytesA);
+  const int nlo = 1 << p.twS, nhi = p.N >> p.twS;
+  VC* twhi = twlo + nlo;
+
+  const int32_t* bs = p.bstart + (int64_t)inst * p.inst_bstart;
+  const int32_t* od = p.ord + (int64_t)inst * p.inst_ord;
+  const int32_t* lm = p.lam + (int64_t)inst * p.inst_lam;
+  const VR* xs = (const VR*)p.x + (int64_t)inst * p.inst_x;
+  for (int b = tid; b <= RR_L; b += 256) bsl[b] = ntaps > 0 ? bs[b] : 0;
+  if constexpr (FFT) {
+    const VC* glo = (const VC*)p.twc_lo;
+    const VC* ghi = (const VC*)p.twc_hi;
+    for (int e = tid; e < nlo + nhi; e += 256) twlo[e] = e < nlo ? glo[e] : ghi[e - nlo];
+  }
+
+  // ---- A(c, l) for l = pl + 16 a, a < 16, summed over the bucket's taps in
+  // bucket order (FP64; stored conjugated for the Fourier class, whose
+  // transform core runs with the + sign)
+  VR acc[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) acc[a] = vzero(VR());
+  const double2* rlo = (const double2*)p.twr_lo;
+  const double2* rhi = (const double2*)p.twr_hi;
+  const uint32_t lomask = (1u << p.twS) - 1u;
+  for (int i0 = 0; i0 < ntaps; i0 += RR_TAPS) {
+    const int nc = min(RR_TAPS, ntaps - i0);
+    __syncthreads();   // bucket starts staged; the previous chunk is consumed
+    if (tid < nc) {
+      const int tau = od[i0 + tid];
+      tl[tid] = lm[tau];
+      tx[tid] = xs[tau];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int l = pl + 16 * a;
+      const int ib = max(bsl[l], i0), ie = min(bsl[l + 1], i0 + nc);
+      for (int i = ib; i < ie; ++i) {
+        const uint32_t lv = (uint32_t)tl[i - i0];
+        const VR xv = tx[i - i0];
+        if constexpr (FFT) {
+          const uint32_t q = (lv * cg) & maskN;
+          const double2 w = cmul(rhi[q >> p.twS], rlo[q & lomask]);
+          acc[a].x += xv.x * w.x + xv.y * w.y;   // conj(x) w
+          acc[a].y += xv.x * w.y - xv.y * w.x;
+        } else {
+          acc[a] += (__popc(lv & mask1 & cg) & 1) ? -xv : xv;
+        }
+      }
+    }
+  }
+  __syncthreads();   // taps consumed: region A becomes the exchange buffers
+
+  // ---- FP64 transform over l: Fourier, lane pl ends with the rows
+  // m = pl + 16 r; Hadamard (l = pl + 16 a in, nibbles swap) m = r + 16 pl
+  if constexpr (FFT) {
+    reg_fft256<true>(acc, xr, pl, [&](int q) { return rhi[q << dsh]; });
+  } else {
+    reg_wht256(acc, xr, pl);
+  }
+
+  // ---- r = y - N^{-1/2} U s at the rows of Omega among the lane's 16 rows.
+  // Column masks: bit m of word m / 32 of column c says whether row c + N1 m
+  // is in Omega; the rank base of that word is the position in y of the
+  // first such row at or after 32 (m / 32).
+  const uint32_t* cm = p.cmask + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
+  const int32_t* cb = p.cbase + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
+  const VR* yv = (const VR*)p.y + (int64_t)inst * p.inst_y;
+  const int ylast = (int)p.inst_y - 1;   // y holds inst_y >= M slots per instance
+  VC rc[16];
+  // four rows at a time, the loads of each group not hoisted above the
+  // previous one (fewer registers live beside the 16 FP64 values)
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    __builtin_amdgcn_sched_barrier(0);
+    VR yy[4];
+    bool pres[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 4 * h + u;
+      const int m = FFT ? pl + 16 * r : r + 16 * pl;
+      const int w = m >> 5;
+      const uint32_t mw = cm[w];
+      const uint32_t bit = (uint32_t)(m & 31);
+      pres[u] = (mw >> bit) & 1u;
+      // unconditional load (rows not in Omega read a valid neighbour, and
+      // their value is discarded), so no branch splits the groups
+      const int rank = cb[w] + __popc(mw & ((1u << bit) - 1u));
+      yy[u] = yv[min(rank, ylast)];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = 4 * h + u;
+      VR X = acc[r];
+      if constexpr (FFT) X = vconj(X);
+      const VR rr = vsub(yy[u], vscale(X, p.rscale));
+      rc[r] = pres[u] ? vnarrow(rr, VC()) : vzero(VC());
+    }
+  }
+
+  // ---- the correlation's first pass over the rows, + sign.  Fourier: rows
+  // m = pl + 16 r in, outputs j2 = pl + 16 r; Hadamard: rows m = r + 16 pl
+  // in, outputs j2 = pl + 16 r
+  if constexpr (FFT) {
+    reg_fft256(rc, xc, pl, [&](int q) { return twhi[q << dsh]; });
+  } else {
+    reg_wht256(rc, xc, pl);
+  }
+  __syncthreads();   // every exchange is done: region A becomes the output tile
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int j2 = pl + 16 * r;
+    VC v = rc[r];
+    if constexpr (FFT) {
+      const uint32_t q = (cg * (uint32_t)j2) & maskN;
+      v = cmul(v, tw_lookup(twlo, twhi, q, p.twS, +1));
+    }
+    tile[j2 * 17 + col] = v;
+  }
+  __syncthreads();
+  VC* out = (VC*)p.out + (int64_t)inst * p.inst_out;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = tid + 256 * k;
+    const int j2 = e >> 4, c = e & 15;
+    out[(int64_t)(s0 + c) + ((int64_t)j2 << p.logN1)] = tile[j2 * 17 + c];
+  }
+}
+
+bool rcorr_reg_ok(int pk, bool fft, const RCParams& p) {
+  return p.L == RR_L && (p.logN1 == 8 || p.logN1 == 9) && p.cmask && p.cbase &&
+         (fft ? (pk == V_C64 || pk == V_C128) : (pk == V_F32 || pk == V_F64));
+}
+
+static size_t rcorr_reg_lds(int pk, bool fft, const RCParams& p) {
+  const size_t bytesA = rr_region_a(vbytes(pk));
+  const size_t ntw = fft ? ((size_t)1 << p.twS) + ((size_t)p.N >> p.twS) : 0;
+  return bytesA + ntw * vbytes(pk);
+}
+
+template <bool FFT, class VC>
+static hipError_t launch_rr(const RCParams& p, int ninst, size_t lds, hipStream_t st) {
+  auto kfn = rcorr_reg_kernel<FFT, VC>;
+  hipError_t e = raise_lds_limit((const void*)kfn, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kfn, dim3((1 << p.logN1) / RR_COLS, ninst), dim3(256), lds, st, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_rcorr_reg(int pk, bool fft, const RCParams& p, int ninst, hipStream_t st) {
+  if (!rcorr_reg_ok(pk, fft, p)) return hipErrorInvalidValue;
+  const size_t lds = rcorr_reg_lds(pk, fft, p);
+  if (fft) {
+    if (pk == V_C64) return launch_rr<true, float2>(p, ninst, lds, st);
+    return launch_rr<true, double2>(p, ninst, lds, st);
+  }
+  if (pk == V_F32) return launch_rr<false, float>(p, ninst, lds, st);
+  return launch_rr<false, double>(p, ninst, lds, st);
+}
+
+}  // namespace fcmp

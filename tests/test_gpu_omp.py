@@ -19,6 +19,8 @@ CASES = [
     ("F", 16384, 4096, 40, "cgauss", 30.0),
     ("H", 65536, 8192, 60, "pm_u12", None),
     ("F", 65536, 16384, 64, "cgauss", 30.0),
+    ("H", 131072, 16384, 48, "gauss", 30.0),
+    ("F", 131072, 32768, 48, "cgauss", 30.0),
 ]
 METHODS = ["conventional", "fast", "adaptive"]
 

@@ -208,3 +208,41 @@ def test_topk_fewer_eligible_than_k(fc):
         bm[j >> 5] &= ~np.uint32(1 << (j & 31))
     out = to_np(fc.topk("H", to_dev(v), K, "fp64", excl=to_dev(bm)))
     assert list(out) == list(keep) + [-1, -1, -1]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("cls", ["H", "F"])
+@pytest.mark.parametrize("N", [1 << 15, 1 << 16, 1 << 17, 1 << 18, 1 << 19, 1 << 20])
+def test_correlate_identification_only(fc, cls, N, precision):
+    """The correlation whose outputs are only identified (the register-resident
+    second pass, rows of 256, 512 or 1024): the fused argmax, with an exclusion
+    bitmap that removes the oracle's top columns, picks the oracle's argmax
+    over the remaining columns when its gap is certified, else a column within
+    tolerance of it."""
+    import torch
+    rng = np.random.default_rng(N + 17)
+    M = N // 4 + 3
+    om = omega(rng, N, M)
+    r = rand_vec(rng, M, _cplx(cls))
+    rd = to_dev(r.astype(np.complex64 if (_cplx(cls) and precision == "fp32") else
+                         np.float32 if precision == "fp32" else r.dtype))
+    rin = to_np(rd).astype(np.complex128 if _cplx(cls) else np.float64)
+    want = oracle.unitary.TransformOperator(cls, N, om).adjoint(rin)
+    a = np.abs(want) ** 2
+    top = np.argsort(-a, kind="stable")[:5]
+    excl = np.zeros(N // 32, dtype=np.uint32)
+    for j in top[:3]:
+        excl[j >> 5] |= np.uint32(1 << (j & 31))
+    ex = torch.from_numpy(excl.view(np.int32)).cuda()
+    for e, skip in ((None, 0), (ex, 3)):
+        h, sel = fc.correlate(cls, N, om, rd, precision, excl=e, want_h=False)
+        assert h is None
+        idx, key = fc.decode_sel(sel)
+        best, second = top[skip], top[skip + 1]
+        gap = (np.sqrt(a[best]) - np.sqrt(a[second])) / np.sqrt(a[top[0]])
+        if gap >= 2.5 * TOL[precision]:
+            assert idx == best
+        else:
+            assert idx not in top[:skip]
+            assert np.sqrt(a[idx]) >= np.sqrt(a[best]) - 2 * TOL[precision] * np.sqrt(a[top[0]])
+        assert abs(np.sqrt(key) - np.sqrt(a[idx])) <= TOL[precision] * np.sqrt(a[top[0]])

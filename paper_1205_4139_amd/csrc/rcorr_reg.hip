@@ -64,52 +64,118 @@ rcorr_reg_kernel(RCParams p) {
   VC* twlo = (VC*)(smem_raw + bytesA);
   const int nlo = 1 << p.twS, nhi = p.N >> p.twS;
   VC* twhi = twlo + nlo;
+  // Fourier: W_N1^q (FP64) for the tap sums, after the correlation twiddles
+  double2* t1 = (double2*)(((uintptr_t)(twhi + (FFT ? nhi : 0)) + 15) & ~(uintptr_t)15);
 
+  // Global loads with no dependence on this workgroup's LDS are issued first,
+  // so their latencies overlap: the first chunk of taps, the tables, the
+  // column masks of the residual and the per-register twiddle factors.
   const int32_t* bs = p.bstart + (int64_t)inst * p.inst_bstart;
   const int32_t* od = p.ord + (int64_t)inst * p.inst_ord;
   const int32_t* lm = p.lam + (int64_t)inst * p.inst_lam;
   const VR* xs = (const VR*)p.x + (int64_t)inst * p.inst_x;
+  int tlv0 = 0;
+  VR txv0 = vzero(VR());
+  if (ntaps > 0) {
+    const int tau = od[min(tid, ntaps - 1)];
+    tlv0 = lm[tau];
+    txv0 = xs[tau];
+  }
+  const uint32_t* cm = p.cmask + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
+  const int32_t* cb = p.cbase + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
+  uint32_t mwv[FFT ? 8 : 1];
+  int32_t bwv[FFT ? 8 : 1];
+#pragma unroll
+  for (int w = 0; w < (FFT ? 8 : 1); ++w) {
+    mwv[w] = cm[FFT ? w : (pl >> 1)];
+    bwv[w] = cb[FFT ? w : (pl >> 1)];
+  }
+  double2 wl0 = make_double2(1.0, 0.0), wl16 = make_double2(1.0, 0.0);
+  if constexpr (FFT) {
+    // W_N^{l c} for l = pl + 16 a is W_N^{pl c} (W_N^{16 c})^a
+    const double2* rlo = (const double2*)p.twr_lo;
+    const double2* rhi = (const double2*)p.twr_hi;
+    const uint32_t lomask = (1u << p.twS) - 1u;
+    const uint32_t q0 = ((uint32_t)pl * cg) & maskN, q1 = (16u * cg) & maskN;
+    wl0 = cmul(rhi[q0 >> p.twS], rlo[q0 & lomask]);
+    wl16 = cmul(rhi[q1 >> p.twS], rlo[q1 & lomask]);
+  }
   for (int b = tid; b <= RR_L; b += 256) bsl[b] = ntaps > 0 ? bs[b] : 0;
   if constexpr (FFT) {
     const VC* glo = (const VC*)p.twc_lo;
     const VC* ghi = (const VC*)p.twc_hi;
     for (int e = tid; e < nlo + nhi; e += 256) twlo[e] = e < nlo ? glo[e] : ghi[e - nlo];
+    const double2* g1 = (const double2*)p.twr_hi;   // W_N^{q N2} = W_N1^q
+    for (int e = tid; e < nhi; e += 256) t1[e] = g1[e];
   }
 
   // ---- A(c, l) for l = pl + 16 a, a < 16, summed over the bucket's taps in
   // bucket order (FP64; stored conjugated for the Fourier class, whose
-  // transform core runs with the + sign)
+  // transform core runs with the + sign).  Fourier: with lam = l + N2 lam2,
+  //   conj(A(c, l)) = W_N^{l c} sum_taps conj(x) W_N1^{lam2 c}   (W_n = e^{+2 pi i / n}),
+  // so a tap costs one lookup in the N1-entry table and one multiply-add; the
+  // factor W_N^{l c} is applied once per register afterwards.
   VR acc[16];
 #pragma unroll
   for (int a = 0; a < 16; ++a) acc[a] = vzero(VR());
-  const double2* rlo = (const double2*)p.twr_lo;
-  const double2* rhi = (const double2*)p.twr_hi;
-  const uint32_t lomask = (1u << p.twS) - 1u;
+  const uint32_t mask1n = (uint32_t)nhi - 1u;   // N1 - 1
   for (int i0 = 0; i0 < ntaps; i0 += RR_TAPS) {
     const int nc = min(RR_TAPS, ntaps - i0);
-    __syncthreads();   // bucket starts staged; the previous chunk is consumed
+    __syncthreads();   // tables staged; the previous chunk is consumed
     if (tid < nc) {
-      const int tau = od[i0 + tid];
-      tl[tid] = lm[tau];
-      tx[tid] = xs[tau];
+      int lv;
+      VR xv;
+      if (i0 == 0) {
+        lv = tlv0;
+        xv = txv0;
+      } else {
+        const int tau = od[i0 + tid];
+        lv = lm[tau];
+        xv = xs[tau];
+      }
+      tl[tid] = FFT ? (lv >> p.twS) : lv;   // Fourier: lam2 = lam / N2
+      tx[tid] = xv;
     }
     __syncthreads();
+    // the first tap of every bucket for the 16 registers at once (independent
+    // lookups in flight; an empty bucket adds a zero), then the rest of each
+    // bucket in order
+    auto add_tap = [&](VR& ac, int li, bool on) {
+      const uint32_t lv = (uint32_t)tl[li];
+      VR xv = tx[li];
+      if (!on) xv = vzero(VR());
+      if constexpr (FFT) {
+        const double2 w = t1[(lv * cg) & mask1n];
+        ac.x += xv.x * w.x + xv.y * w.y;   // conj(x) w
+        ac.y += xv.x * w.y - xv.y * w.x;
+      } else {
+        ac += (__popc(lv & mask1 & cg) & 1) ? -xv : xv;
+      }
+    };
+#pragma unroll
+    for (int a0 = 0; a0 < 16; a0 += 4) {
+      int ib[4], ie[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int l = pl + 16 * (a0 + u);
+        ib[u] = max(bsl[l], i0) - i0;
+        ie[u] = min(bsl[l + 1], i0 + nc) - i0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) add_tap(acc[a0 + u], min(ib[u], nc - 1), ib[u] < ie[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        for (int i = ib[u] + 1; i < ie[u]; ++i) add_tap(acc[a0 + u], i, true);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  if constexpr (FFT) {
+    // the factor W_N^{l c}, powers by repeated multiplication (FP64)
+    double2 w = wl0;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
-      const int l = pl + 16 * a;
-      const int ib = max(bsl[l], i0), ie = min(bsl[l + 1], i0 + nc);
-      for (int i = ib; i < ie; ++i) {
-        const uint32_t lv = (uint32_t)tl[i - i0];
-        const VR xv = tx[i - i0];
-        if constexpr (FFT) {
-          const uint32_t q = (lv * cg) & maskN;
-          const double2 w = cmul(rhi[q >> p.twS], rlo[q & lomask]);
-          acc[a].x += xv.x * w.x + xv.y * w.y;   // conj(x) w
-          acc[a].y += xv.x * w.y - xv.y * w.x;
-        } else {
-          acc[a] += (__popc(lv & mask1 & cg) & 1) ? -xv : xv;
-        }
-      }
+      acc[a] = cmul(acc[a], w);
+      if (a < 15) w = cmul(w, wl16);
     }
   }
   __syncthreads();   // taps consumed: region A becomes the exchange buffers
@@ -117,7 +183,7 @@ rcorr_reg_kernel(RCParams p) {
   // ---- FP64 transform over l: Fourier, lane pl ends with the rows
   // m = pl + 16 r; Hadamard (l = pl + 16 a in, nibbles swap) m = r + 16 pl
   if constexpr (FFT) {
-    reg_fft256<true>(acc, xr, pl, [&](int q) { return rhi[q << dsh]; });
+    reg_fft256<true>(acc, xr, pl, [&](int q) { return t1[q << dsh]; });
   } else {
     reg_wht256(acc, xr, pl);
   }
@@ -126,8 +192,6 @@ rcorr_reg_kernel(RCParams p) {
   // Column masks: bit m of word m / 32 of column c says whether row c + N1 m
   // is in Omega; the rank base of that word is the position in y of the
   // first such row at or after 32 (m / 32).
-  const uint32_t* cm = p.cmask + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
-  const int32_t* cb = p.cbase + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
   const VR* yv = (const VR*)p.y + (int64_t)inst * p.inst_y;
   const int ylast = (int)p.inst_y - 1;   // y holds inst_y >= M slots per instance
   VC rc[16];
@@ -142,13 +206,13 @@ rcorr_reg_kernel(RCParams p) {
     for (int u = 0; u < 4; ++u) {
       const int r = 4 * h + u;
       const int m = FFT ? pl + 16 * r : r + 16 * pl;
-      const int w = m >> 5;
-      const uint32_t mw = cm[w];
+      const int w = FFT ? (m >> 5) : 0;
+      const uint32_t mw = mwv[w];
       const uint32_t bit = (uint32_t)(m & 31);
       pres[u] = (mw >> bit) & 1u;
       // unconditional load (rows not in Omega read a valid neighbour, and
       // their value is discarded), so no branch splits the groups
-      const int rank = cb[w] + __popc(mw & ((1u << bit) - 1u));
+      const int rank = bwv[w] + __popc(mw & ((1u << bit) - 1u));
       yy[u] = yv[min(rank, ylast)];
     }
 #pragma unroll
@@ -198,7 +262,8 @@ bool rcorr_reg_ok(int pk, bool fft, const RCParams& p) {
 static size_t rcorr_reg_lds(int pk, bool fft, const RCParams& p) {
   const size_t bytesA = rr_region_a(vbytes(pk));
   const size_t ntw = fft ? ((size_t)1 << p.twS) + ((size_t)p.N >> p.twS) : 0;
-  return bytesA + ntw * vbytes(pk);
+  const size_t t1b = fft ? ((size_t)p.N >> p.twS) * 16 + 16 : 0;
+  return bytesA + ntw * vbytes(pk) + t1b;
 }
 
 template <bool FFT, class VC>

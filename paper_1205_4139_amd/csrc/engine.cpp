@@ -170,6 +170,7 @@ void build_tables(const Geo& g, const int32_t* omega, int M, HostTables& t) {
     }
     t.goff.assign(g.ngroups + 1, 0);
     for (int q = 0; q <= g.ngroups; ++q) t.goff[q] = cst[std::min(N1, q << logB1)];
+    t.cst = cst;
   }
   // rows grouped by the pass-2 workgroup that produces them (Fourier output
   // j = j2 + N2 j1, Hadamard output j = j1 + N1 j2); pos1 maps back to the

@@ -70,6 +70,7 @@ int pick_threads(int tile_n);                    // threads of a transform workg
 struct HostTables {
   std::vector<int32_t> ent_k, perm, goff;   // entry order (grouped or Omega order)
   std::vector<int32_t> ent2_k, goff2, pos1; // rows grouped by pass-2 output workgroup
+  std::vector<int32_t> cst;                 // grouped: first entry of each column (N1 + 1)
   std::vector<uint32_t> cmask;              // grouped: rows of Omega per column (N / 32 words)
   std::vector<int32_t> cbase;               //   and the entry index of each word's first row
   std::vector<double2> tw64;                // lo (2^twS), hi (N >> twS), stage table; sign +

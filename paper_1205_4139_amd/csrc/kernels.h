@@ -101,7 +101,8 @@ struct RCParams {
   int L, logL, B, logN1;   // L = N2 and B columns (k mod N1) per workgroup
   const int32_t* lam; const void* x; const int32_t* ord; const int32_t* bstart; int ntaps;
   int64_t inst_lam, inst_x, inst_ord, inst_bstart;
-  const int32_t* ent_k; const int32_t* goff;   // rows of Omega, grouped per workgroup
+  const int32_t* ent_k;    // rows of Omega, sorted by column (k mod N1), then by row
+  const int32_t* goff;     // entry index of the first row of each column (N1 + 1 values)
   const void* y;           // FP64 (wide) in entry order
   int64_t inst_ent, inst_goff, inst_y;
   double rscale;           // N^{-1/2}

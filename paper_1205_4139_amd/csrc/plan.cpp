@@ -19,12 +19,25 @@ static int64_t pad64(int64_t v) { return (v + 63) & ~int64_t(63); }
 
 // Geometry of the fused residual + first-pass launch: the correlation's
 // first pass (B1 columns of length N2 per workgroup).
+// Columns per workgroup of the fused pass: the most whose tile fits the
+// kernel (at most 2048 values, 64 KiB of LDS), a function of (class, N,
+// precision) only, so whether a plan fuses the residual never depends on the
+// plan's size or launch knobs.
 RCParams rcorr_geometry(const fcmp_plan& P) {
   RCParams q{};
   q.N = P.g.N; q.logN = P.g.logN; q.twS = P.g.twS;
-  q.L = 1 << P.g.n2; q.logL = P.g.n2; q.B = P.g.B1; q.logN1 = P.g.n1;
+  q.L = 1 << P.g.n2; q.logL = P.g.n2; q.logN1 = P.g.n1;
+  const int N1 = 1 << P.g.n1;
+  int best = 1;
+  for (int b = 1; b <= N1 && b * q.L <= 2048; b *= 2) {
+    q.B = b;
+    if (rcorr_ok(P.pk, P.g.fourier, q, rcorr_threads(q))) best = b;
+  }
+  q.B = best;
   return q;
 }
+
+int rcorr_threads(const RCParams& q) { return std::min(256, std::max(64, q.B * q.L / 8)); }
 
 int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt) {
   if (n < 1) return set_error(FCMP_E_INVALID, "n must be >= 1");
@@ -76,9 +89,10 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
     q.cmask = (const uint32_t*)&P;   // presence only: the tables are laid out below
     q.cbase = (const int32_t*)&P;
     P.rreg = rcorr_reg_ok(P.pk, F, q);
-    P.fused = P.rreg || rcorr_ok(P.pk, F, q, pick_threads(q.B * q.L));
+    P.fused = P.rreg || rcorr_ok(P.pk, F, q, rcorr_threads(q));
   }
   P.sC = pad64(N / 32);
+  P.sCs = pad64(((int64_t)1 << P.g.n1) + 1);
   P.sB = pad64(((int64_t)1 << P.g.n2) + 1);
   P.npart = std::max(transform_partials_max(P.g), fastcorr_groups((int)N));
   P.sP = pad64(P.npart);
@@ -114,6 +128,7 @@ void plan_layout(fcmp_plan& P, char* base) {
     P.cmask = nullptr;
     P.cbase = nullptr;
   }
+  P.cst = (P.fused && !P.rreg) ? cv.take<int32_t>(n * P.sCs) : nullptr;
   if (!P.uniform) {
     P.Mv = cv.take<int32_t>(n);
     P.Kv = cv.take<int32_t>(n);
@@ -190,8 +205,9 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
   const int64_t n = P.n;
   std::vector<int32_t> ent((size_t)(n * P.sM), 0), perm((size_t)(n * P.sM), 0),
       goff((size_t)(n * P.sG), 0);
-  std::vector<int32_t> ent2, goff2, pos1, cbase;
+  std::vector<int32_t> ent2, goff2, pos1, cbase, cst;
   std::vector<uint32_t> cmask;
+  if (P.cst) cst.assign((size_t)(n * P.sCs), 0);
   if (P.rreg) {
     cmask.assign((size_t)(n * P.sC), 0u);
     cbase.assign((size_t)(n * P.sC), 0);
@@ -212,6 +228,7 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
       std::memcpy(&cmask[b * P.sC], t.cmask.data(), t.cmask.size() * 4);
       std::memcpy(&cbase[b * P.sC], t.cbase.data(), t.cbase.size() * 4);
     }
+    if (P.cst) std::memcpy(&cst[b * P.sCs], t.cst.data(), t.cst.size() * 4);
     if (!P.g.same_out) {
       std::memcpy(&ent2[b * P.sM], t.ent2_k.data(), M * 4);
       std::memcpy(&goff2[b * P.sG2], t.goff2.data(), t.goff2.size() * 4);
@@ -223,6 +240,8 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(P.goff2, goff2.data(), goff2.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(P.pos1, pos1.data(), pos1.size() * 4, hipMemcpyHostToDevice, st));
   }
+  if (P.cst)
+    HIP_TRY(hipMemcpyAsync(P.cst, cst.data(), cst.size() * 4, hipMemcpyHostToDevice, st));
   if (P.rreg) {
     HIP_TRY(hipMemcpyAsync(P.cmask, cmask.data(), cmask.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(P.cbase, cbase.data(), cbase.size() * 4, hipMemcpyHostToDevice, st));
@@ -373,8 +392,8 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
     q.ord = P.ord + (ntaps & 1) * P.sK;
     q.bstart = P.bst + (ntaps & 1) * P.sB;
     q.inst_lam = P.sK; q.inst_x = P.sK; q.inst_ord = 2 * P.sK; q.inst_bstart = 2 * P.sB;
-    q.ent_k = P.ent_k; q.goff = P.goff; q.y = P.y_ent;
-    q.inst_ent = P.sM; q.inst_goff = P.sG; q.inst_y = P.sM;
+    q.ent_k = P.ent_k; q.goff = P.cst; q.y = P.y_ent;
+    q.inst_ent = P.sM; q.inst_goff = P.sCs; q.inst_y = P.sM;
     q.rscale = inv_sqrt_n;
     const TwDev tr = tw_for(P, P.wk), tc = tw_for(P, P.pk);
     q.twr_lo = tr.lo; q.twr_hi = tr.hi; q.twr_st = tr.st;
@@ -383,7 +402,7 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
     q.status = P.status;
     q.cmask = P.cmask; q.cbase = P.cbase; q.inst_cmask = P.sC;
     if (P.rreg) HIP_TRY(launch_rcorr_reg(P.pk, F, q, n, st));
-    else HIP_TRY(launch_rcorr(P.pk, F, q, (1 << g.n1) / g.B1, n, pick_threads(q.B * q.L), st));
+    else HIP_TRY(launch_rcorr(P.pk, F, q, (1 << g.n1) / q.B, n, rcorr_threads(q), st));
     XDst d;
     d.partial = P.partial; d.excl = P.excl;
     d.scale = inv_sqrt_n;

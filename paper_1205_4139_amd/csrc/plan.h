@@ -35,6 +35,8 @@ struct fcmp_plan {
   uint32_t* cmask = nullptr;   // register-resident fused residual: rows of Omega
   int32_t* cbase = nullptr;    //   per column and their positions in y
   int64_t sC = 0;              //   words per instance (N / 32, padded)
+  int32_t* cst = nullptr;      // fused residual (other N): first entry of each column
+  int64_t sCs = 0;             //   N1 + 1 values per instance, padded
   void* c64 = nullptr;
   void* cp = nullptr;
   int16_t* ci16 = nullptr;     // Hadamard, M < 2^15: the integers N c (fast gathers)
@@ -98,6 +100,7 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st);
 int plan_set_tap_order(fcmp_plan& P, const int32_t* lam, int ntaps, hipStream_t st,
                        std::vector<int32_t>& ord, std::vector<int32_t>& bst);
 RCParams rcorr_geometry(const fcmp_plan& P);
+int rcorr_threads(const RCParams& q);
 // Fills stats from host copies of the status records; FCMP_E_NUMERIC when any
 // instance broke down.
 int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats);

@@ -72,8 +72,10 @@ __global__ void __launch_bounds__(256) rcorr_kernel(RCParams p) {
   }
   const int b0 = ntaps > 0 ? bs[min(tid, L)] : 0;
   const int b1 = ntaps > 0 ? bs[min(tid + nt, L)] : 0;
+  // entries are sorted by column: this workgroup's rows of Omega are those
+  // of columns s0 .. s0 + B - 1
   const int32_t* go = p.goff + (int64_t)inst * p.inst_goff;
-  const int lo = go[g], hi = go[g + 1];
+  const int lo = go[s0], hi = go[s0 + B];
   const int32_t* ek = p.ent_k + (int64_t)inst * p.inst_ent;
   const VR* yv = (const VR*)p.y + (int64_t)inst * p.inst_y;
   bsl[min(tid, L)] = b0;

@@ -310,3 +310,23 @@ def test_hadamard_integer_kernel_bit_identical(fc, method, precision):
         ref = oracle.omp(oracle.make_operator("H", 4096, inst.omega), y, 37)
         if certify.certified(ref, precision):
             assert list(s1[b]) == list(ref.support)
+
+
+def test_fused_residual_choice_independent_of_plan_size(fc):
+    """Whether the residual is fused into the correlation's first pass
+    depends on (class, N, precision) only: complex128 Fourier N = 2^20 (the
+    non-register fused kernel) solved in a plan of 34 instances and alone
+    gives bit-identical supports and x."""
+    import torch
+    N, M, K = 1 << 20, 1 << 17, 6
+    data = _insts("F", N, M, K, "cgauss", 30.0, 34, 8500)
+    plan = fc.Plan("F", N, M, K, [d[0].omega for d in data], precision="fp64")
+    ys = torch.stack([to_dev(d[1]) for d in data])
+    sup, x, _ = plan.solve(ys)
+    sup, x = to_np(sup).copy(), to_np(x).copy()
+    plan.close()
+    for b in (0, 33):
+        inst, y = data[b]
+        alone = fc.solve("F", N, M, K, inst.omega, to_dev(y), precision="fp64")
+        assert np.array_equal(to_np(alone.support), sup[b])
+        assert np.array_equal(to_np(alone.x), x[b])

@@ -102,3 +102,17 @@ def test_omp_long_support_residual_paths(fc, case, precision, resid, monkeypatch
         assert np.linalg.norm(to_np(res.x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
         checked += 1
     assert checked >= 1
+
+
+@pytest.mark.parametrize("cls", ["H", "F"])
+def test_omp_more_taps_than_one_staged_chunk(fc, cls):
+    """K = 300: the fused residual stages its taps in chunks of 256, so the
+    last iterations take two chunks.  N = 65536, M = 16384, noiseless
+    +-U(1,2) values (seed 7100, certified at FP64 but not at FP32), FP64
+    correlation: the support matches the oracle's selection order and x
+    agrees to 1e-10."""
+    inst, y, ref = _reference((cls, 65536, 16384, 300, "pm_u12", None), 7100)
+    assert certify.certified(ref, "fp64")
+    res = fc.solve(cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y), precision="fp64")
+    assert list(to_np(res.support)) == list(ref.support)
+    assert np.linalg.norm(to_np(res.x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)

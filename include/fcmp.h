@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define FCMP_ABI_VERSION 1
+#define FCMP_ABI_VERSION 2
 
 /* status codes */
 #define FCMP_OK            0
@@ -100,7 +100,11 @@ typedef struct {
   int32_t switch_t;          /* ADAPTIVE: last iteration that uses the fast method
                                 (0 = library's tuned value) */
   uint32_t flags;            /* FCMP_FLAG_* */
-  double  res_tol;           /* reserved, must be 0 */
+  double  res_tol;           /* optional halting rule (Algorithm 1.1 step 8):
+                                OMP stops after the first selection whose
+                                residual meets ||r|| <= res_tol ||y||; SP and
+                                CoSaMP stop their loop once it is met.
+                                0 = off; must be in [0, 1). */
 } fcmp_options;
 
 /* fcmp_plan_solve recomputes the kernel vector (A1) instead of reusing the
@@ -124,11 +128,29 @@ typedef struct {
  * ones, so results agree with the full gathers to rounding, not bit for bit.
  * Ignored for the Hadamard class and by the persistent batch kernel. */
 #define FCMP_FLAG_HALF_KERNEL 8u
+/* Fill the ms_corr / ms_select / ms_ls / ms_resid fields of fcmp_stats:
+ * every phase's launch sequence of this solve is bracketed by hipEvents on
+ * the solve's stream (a small overhead per launch).  Ignored under graph
+ * capture and by the persistent batch kernel. */
+#define FCMP_FLAG_PHASE_TIMES 16u
 
+/* Per-solve statistics. */
 typedef struct {
   int32_t iterations;        /* OMP: selections made; SP/CoSaMP: outer iterations */
-  int32_t status;            /* FCMP_OK or FCMP_E_NUMERIC */
+  int32_t status_detail;     /* FCMP_OK or FCMP_E_NUMERIC (Cholesky breakdown) */
   double  res_norm;          /* ||y - Phi_Lambda x|| (from the normal equations) */
+  double  min_gap;           /* OMP: smallest identification gap over the solve,
+                                (|h|_(1) - |h|_(2)) / |h|_(1) over the columns not
+                                yet selected, keys in the correlation precision
+                                (1 when a selection had no runner-up, +inf
+                                before the first); SP/CoSaMP: NaN (not tracked) */
+  float   ms_corr;           /* with FCMP_FLAG_PHASE_TIMES (else 0), device time
+                                of this solve's phases, ms: correlation (h_0,
+                                conventional incl. a fused residual, fast) */
+  float   ms_select;         /*   SP/CoSaMP top-K selection (OMP's argmax is
+                                fused into the correlation and least squares) */
+  float   ms_ls;             /*   identification merge + least squares */
+  float   ms_resid;          /*   residual computed apart from the correlation */
   double  ms_total;          /* device time of the solve (hipEvent), ms; for a
                                 problem run by the persistent batch kernel: its
                                 completion time from the start of the batch */
@@ -344,6 +366,7 @@ int fcmp_adaptive_switch(int32_t matrix_class, int64_t N, int32_t corr_precision
 #define FCMP_PHASE_RESID  4   /* residual r = y - Phi_t x_t, when computed apart  */
 #define FCMP_PHASE_LS     5   /* identification + least-squares update           */
 #define FCMP_PHASE_OTHER  6   /* gathers, status, copy-out                        */
+#define FCMP_PHASE_SELECT 7   /* SP/CoSaMP top-K selection                        */
 #define FCMP_NPHASE       8
 typedef struct {
   double  ms[FCMP_NPHASE];

@@ -13,7 +13,9 @@ update (step 7).  With ``method="fast"`` step 2 is replaced by eq.
 Readings where the paper is silent (each listed in the design notes):
 * identification compares |h|^2 over the columns not yet selected; ties go
   to the lowest index; if that maximum is exactly 0 the loop stops early;
-* halting: OMP runs exactly K iterations;
+* halting: OMP runs exactly K iterations, or (optional residual rule,
+  Algorithm 1.1 step 8 leaves the criterion open) stops after the first
+  iteration whose residual satisfies ||r|| <= res_tol ||y||;
 * least squares uses LAPACK lstsq on the explicit selected columns.
 
 SP and CoSaMP are only cited by the paper (Sec. I, Sec. IV); the loops below
@@ -94,8 +96,9 @@ class OmpResult:
 
 
 def omp(op: Operator, y, K: int, method: str = "conventional",
-        keep_h: bool = False, c=None) -> OmpResult:
-    """Algorithm 1.1 for exactly K iterations (early stop if max |h| = 0)."""
+        keep_h: bool = False, c=None, res_tol: float = 0.0) -> OmpResult:
+    """Algorithm 1.1 for exactly K iterations (early stop if max |h| = 0, or,
+    with res_tol > 0, once ||r|| <= res_tol ||y||)."""
     y = np.asarray(y)
     N = op.N
     r = y.copy()                                       # step 1
@@ -133,6 +136,8 @@ def omp(op: Operator, y, K: int, method: str = "conventional",
         r = y - Phi_t @ x                              # step 7
         if keep_h:
             xs.append(x.copy())
+        if res_tol > 0.0 and np.linalg.norm(r) <= res_tol * np.linalg.norm(y):
+            break                                      # step 8 (residual rule)
     res.support = np.asarray(lam, dtype=np.int64)
     res.x = x
     res.iterations = len(lam)
@@ -164,11 +169,12 @@ def _sorted_pair(idx, val):
 
 
 def sp(op: Operator, y, K: int, method: str = "conventional",
-       max_iter: int = 50, c=None) -> SetResult:
+       max_iter: int = 50, c=None, res_tol: float = 0.0) -> SetResult:
     """Subspace pursuit (reading): start from the K largest |h_0|; each
     iteration merges the K largest |Phi^H r| outside T, fits on the 2K merged
     columns, keeps the K largest |x|, refits, and stops when the support
-    repeats or the residual stops shrinking (keeping the previous one)."""
+    repeats or the residual stops shrinking (keeping the previous one), or,
+    with res_tol > 0, before an iteration once ||r|| <= res_tol ||y||."""
     y = np.asarray(y)
     h0 = op.adjoint(y)
     if method == "fast" and c is None:
@@ -179,7 +185,8 @@ def sp(op: Operator, y, K: int, method: str = "conventional",
     rn = np.linalg.norm(r)
     out = SetResult(T, x, 0, float(rn), [T.copy()])
     it = 0
-    while it < max_iter:
+    ny = np.linalg.norm(y)
+    while it < max_iter and not (res_tol > 0.0 and rn <= res_tol * ny):
         it += 1
         h = _correlate(op, method, r, h0, c, T, x)
         extra = topk(_mag2(h), K, excluded=T)
@@ -205,11 +212,12 @@ def sp(op: Operator, y, K: int, method: str = "conventional",
 
 
 def cosamp(op: Operator, y, K: int, method: str = "conventional",
-           max_iter: int = 50, c=None) -> SetResult:
+           max_iter: int = 50, c=None, res_tol: float = 0.0) -> SetResult:
     """CoSaMP (reading): proxy Phi^H v, merge its 2K largest with the current
     support, fit on the merged columns, prune to the K largest (no refit in
     the loop), update v = y - Phi a; stop when the support repeats, when
-    ||v|| <= 1e-12 ||y||, or after max_iter; finally refit on the support."""
+    ||v|| <= 1e-12 ||y|| (or <= res_tol ||y|| with res_tol > 0), or after
+    max_iter; finally refit on the support."""
     y = np.asarray(y)
     ny = np.linalg.norm(y)
     h0 = op.adjoint(y)
@@ -232,7 +240,8 @@ def cosamp(op: Operator, y, K: int, method: str = "conventional",
         changed = not np.array_equal(Sn, S)
         S, a = Sn, an
         out.supports.append(S.copy())
-        if not changed or np.linalg.norm(v) <= 1e-12 * ny:
+        vn = np.linalg.norm(v)
+        if not changed or vn <= 1e-12 * ny or (res_tol > 0.0 and vn <= res_tol * ny):
             break
     x = lstsq(op.columns(S), y)
     out.support, out.x = S, x

@@ -55,13 +55,17 @@ class Options(ctypes.Structure):
 
 
 class Stats(ctypes.Structure):
-    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("res_norm", ctypes.c_double), ("ms_total", ctypes.c_double)]
+    _fields_ = [("iterations", ctypes.c_int32), ("status_detail", ctypes.c_int32),
+                ("res_norm", ctypes.c_double), ("min_gap", ctypes.c_double),
+                ("ms_corr", ctypes.c_float), ("ms_select", ctypes.c_float),
+                ("ms_ls", ctypes.c_float), ("ms_resid", ctypes.c_float),
+                ("ms_total", ctypes.c_double)]
 
 
 NPHASE = 8
-PHASES = ["kernel", "h0", "corr", "fast", "resid", "ls", "other"]
+PHASES = ["kernel", "h0", "corr", "fast", "resid", "ls", "other", "select"]
 FLAG_RECOMPUTE_KERNEL = 1
+FLAG_PHASE_TIMES = 16
 
 
 class ServerConfig(ctypes.Structure):
@@ -163,9 +167,10 @@ def make_problem(cls, N: int, M: int, K: int, omega) -> tuple:
 
 
 def make_options(algorithm="omp", method="conventional", precision="fp64",
-                 max_iter=0, switch_t=0, flags=0) -> Options:
+                 max_iter=0, switch_t=0, flags=0, res_tol=0.0) -> Options:
     return Options(ALGO.get(algorithm, algorithm), METHOD.get(method, method),
-                   PREC.get(precision, precision), int(max_iter), int(switch_t), int(flags), 0.0)
+                   PREC.get(precision, precision), int(max_iter), int(switch_t), int(flags),
+                   float(res_tol))
 
 
 # ---------------------------------------------------------------- torch glue
@@ -213,10 +218,11 @@ def query_workspace(cls, N, M, K, omega, algorithm="omp", method="conventional",
 
 
 def solve(cls, N, M, K, omega, y, algorithm="omp", method="conventional", precision="fp64",
-          switch_t=0, max_iter=0, stats=True, workspace=None) -> SolveResult:
+          switch_t=0, max_iter=0, stats=True, workspace=None, flags=0,
+          res_tol=0.0) -> SolveResult:
     torch = _torch()
     p, _om = make_problem(cls, N, M, K, omega)
-    o = make_options(algorithm, method, precision, max_iter, switch_t)
+    o = make_options(algorithm, method, precision, max_iter, switch_t, flags, res_tol)
     n = ctypes.c_size_t(0)
     _check(lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)))
     dev = y.device
@@ -367,11 +373,11 @@ class Plan:
         self.support = torch.empty((self.n, self.K), dtype=torch.int32, device=device)
         self.x = torch.empty((self.n, self.K), dtype=_dtype(cls), device=device)
 
-    def solve(self, ys, method=None, switch_t=0, flags=0, stats=False):
+    def solve(self, ys, method=None, switch_t=0, flags=0, stats=False, res_tol=0.0):
         """ys: tensor [n, M] (or list of n tensors).  Returns (support [n, K],
         x [n, K], stats list or None); outputs are overwritten by the next solve."""
         o = make_options(self.algorithm, method or METHOD_NAME[self.opt.corr_method],
-                         self.precision, self.opt.max_iter, switch_t, flags)
+                         self.precision, self.opt.max_iter, switch_t, flags, res_tol)
         if hasattr(ys, "dim") and ys.dim() == 2:
             yp = [ys.data_ptr() + i * ys.stride(0) * ys.element_size() for i in range(self.n)]
         else:
@@ -415,7 +421,7 @@ FLAG_HALF_KERNEL = 8
 
 
 def batch_solve(problems, ys, algorithm="omp", method="conventional", precision="fp64",
-                switch_t=0, device="cuda", flags=0, stats=True):
+                switch_t=0, device="cuda", flags=0, stats=True, res_tol=0.0):
     """Mixed-shape batch.  problems: list of (cls, N, M, K, omega); ys: list of
     device tensors.  Returns (supports, xs, stats) as lists."""
     torch = _torch()
@@ -425,7 +431,7 @@ def batch_solve(problems, ys, algorithm="omp", method="conventional", precision=
     for i, (cls, N, M, K, _o) in enumerate(problems):
         probs[i] = Problem(CLASS[cls], 0, int(N), int(M), int(K),
                            oms[i].ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
-    o = make_options(algorithm, method, precision, 0, switch_t, flags)
+    o = make_options(algorithm, method, precision, 0, switch_t, flags, res_tol)
     nb = ctypes.c_size_t(0)
     _check(lib.fcmp_batch_query_workspace(n, probs, ctypes.byref(o), ctypes.byref(nb)))
     ws = _workspace(nb.value, device)

@@ -235,7 +235,8 @@ int wg_run(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
       const int c = (int)G.count;
       HIP_TRY(launch_gather_ptr(wk, (const void* const*)(B.ptrs + G.first), G.perm, G.y_ent,
                                 G.M, G.sM, G.sM, c, st));
-      HIP_TRY(launch_init_status(B.status + G.first, G.y_ent, G.M, F, G.sM, c, st));
+      HIP_TRY(launch_init_status(B.status + G.first, G.y_ent, G.M, F, G.sM, c, st, nullptr,
+                                 B.opt.res_tol * B.opt.res_tol));
       const size_t nlo = (size_t)1 << G.g.twS;
       const size_t nhi = (size_t)G.N >> G.g.twS;
       const TwDev tw{G.tw64, G.tw64 + nlo, G.tw64 + nlo + nhi};
@@ -301,8 +302,10 @@ int wg_stats(WgBatch& B, fcmp_stats* stats, hipStream_t st) {
     int worst = FCMP_OK;
     for (int64_t q = 0; q < n; ++q) {
       fcmp_stats& s = stats[B.order_ids[q]];
+      s = fcmp_stats{};
       s.iterations = hs[q].iterations;
-      s.status = hs[q].numeric ? FCMP_E_NUMERIC : FCMP_OK;
+      s.status_detail = hs[q].numeric ? FCMP_E_NUMERIC : FCMP_OK;
+      s.min_gap = hs[q].min_gap;
       const double r2 = hs[q].ynorm2 - hs[q].znorm2;
       s.res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
       s.ms_total = hs[q].t_done / (double)khz;   // completion, from the batch start

@@ -66,44 +66,81 @@ __device__ inline double2 vwiden(float2 a)  { return make_double2((double)a.x, (
 __device__ inline double2 vwiden(double2 a) { return a; }
 
 // ---------------------------------------------------------------- selection
-// Identification key: larger |h|^2 wins, ties go to the lower index.
+// Identification key: larger |h|^2 wins, ties go to the lower index.  key2
+// carries the runner-up's key (the largest key among the other candidates),
+// from which a solve reports its identification gap.
 struct Sel {
   double key;   // |h|^2, or -1 when nothing was eligible
   int64_t idx;  // column index, -1 when nothing was eligible
+  double key2;  // runner-up |h|^2, or -1 when there was no other candidate
 };
 
 __device__ inline bool sel_better(double k1, int64_t i1, double k2, int64_t i2) {
   return (k1 > k2) || (k1 == k2 && (uint64_t)i1 < (uint64_t)i2);
 }
 
-// Wave64 reduction of (key, idx) by xor shuffles.
-__device__ inline void wave_sel_reduce(double& key, int64_t& idx) {
+// Adds one candidate (k, i) to a running (best, runner-up): the loser of the
+// comparison becomes a runner-up candidate.
+template <class K>
+__device__ inline void sel_add(K k, int64_t i, K& key, int64_t& idx, K& key2) {
+  if (sel_better((double)k, i, (double)key, idx)) {
+    key2 = key > key2 ? key : key2;
+    key = k;
+    idx = i;
+  } else if (k > key2) {
+    key2 = k;
+  }
+}
+
+// Merges another (best, runner-up) into a running one.
+__device__ inline void sel_merge(double ok, int64_t oi, double ok2, double& key, int64_t& idx,
+                                 double& key2) {
+  if (sel_better(ok, oi, key, idx)) {
+    key2 = key > ok2 ? key : ok2;
+    key = ok;
+    idx = oi;
+  } else {
+    key2 = ok > key2 ? ok : key2;
+  }
+}
+
+// Wave64 reduction of (key, idx, key2) by xor shuffles.
+__device__ inline void wave_sel_reduce(double& key, int64_t& idx, double& key2) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    double ok = __shfl_xor(key, off, 64);
-    int64_t oi = __shfl_xor(idx, off, 64);
-    if (sel_better(ok, oi, key, idx)) { key = ok; idx = oi; }
+    const double ok = __shfl_xor(key, off, 64);
+    const int64_t oi = __shfl_xor(idx, off, 64);
+    const double ok2 = __shfl_xor(key2, off, 64);
+    sel_merge(ok, oi, ok2, key, idx, key2);
   }
 }
 
 // Block reduction; every thread must call it.  scratch: >= 2*(nwaves) slots.
-__device__ inline Sel block_sel_reduce(double key, int64_t idx, Sel* scratch) {
-  wave_sel_reduce(key, idx);
+__device__ inline Sel block_sel_reduce(double key, int64_t idx, double key2, Sel* scratch) {
+  wave_sel_reduce(key, idx, key2);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = (blockDim.x + 63) >> 6;
-  if (lane == 0) scratch[wave] = Sel{key, idx};
+  if (lane == 0) scratch[wave] = Sel{key, idx, key2};
   __syncthreads();
   if (wave == 0) {
-    Sel s = lane < nwaves ? scratch[lane] : Sel{-1.0, -1};
-    double k = s.key;
+    Sel s = lane < nwaves ? scratch[lane] : Sel{-1.0, -1, -1.0};
+    double k = s.key, k2 = s.key2;
     int64_t i = s.idx;
-    wave_sel_reduce(k, i);
-    if (lane == 0) scratch[0] = Sel{k, i};
+    wave_sel_reduce(k, i, k2);
+    if (lane == 0) scratch[0] = Sel{k, i, k2};
   }
   __syncthreads();
   Sel r = scratch[0];
   __syncthreads();
   return r;
+}
+
+// Relative identification gap (|h|_(1) - |h|_(2)) / |h|_(1) from the keys
+// |h|^2 of a winner and its runner-up (1 when there is no runner-up).
+__device__ inline double sel_gap(const Sel& s) {
+  if (!(s.key > 0.0)) return 0.0;
+  const double a = sqrt(s.key);
+  return s.key2 > 0.0 ? (a - sqrt(s.key2)) / a : 1.0;
 }
 
 __device__ inline double wave_sum(double v) {
@@ -147,6 +184,8 @@ struct Status {
   double  ynorm2;      // ||y||^2
   double  last_key;    // |h|^2 of the last pick
   double  t_done;      // persistent batches: device wall-clock ticks at completion
+  double  min_gap;     // smallest identification gap so far (+inf before any)
+  double  res_tol2;    // stop once ||r||^2 <= res_tol2 ||y||^2 (0: never)
 };
 
 }  // namespace fcmp

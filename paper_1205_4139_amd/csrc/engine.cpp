@@ -380,9 +380,10 @@ int validate_options(const fcmp_problem* p, const fcmp_options* o) {
     return set_error(FCMP_E_INVALID, "unknown corr_precision");
   if (o->max_iter < 0) return set_error(FCMP_E_INVALID, "max_iter must be >= 0");
   if (o->switch_t < 0) return set_error(FCMP_E_INVALID, "switch_t must be >= 0");
-  if (o->res_tol != 0.0) return set_error(FCMP_E_INVALID, "res_tol is reserved and must be 0");
+  if (!(o->res_tol >= 0.0 && o->res_tol < 1.0))
+    return set_error(FCMP_E_INVALID, "res_tol must be in [0, 1)");
   if (o->flags & ~(FCMP_FLAG_RECOMPUTE_KERNEL | FCMP_FLAG_NO_PERSISTENT | FCMP_FLAG_FLOAT_KERNEL |
-                   FCMP_FLAG_HALF_KERNEL))
+                   FCMP_FLAG_HALF_KERNEL | FCMP_FLAG_PHASE_TIMES))
     return set_error(FCMP_E_INVALID, "unknown flags");
   if (o->algorithm == FCMP_OMP && p->K > 4096)
     return set_error(FCMP_E_INVALID, "OMP supports K <= 4096");

@@ -127,8 +127,31 @@ struct Carver {
   size_t total() const { return (off + 255) & ~(size_t)255; }
 };
 
+// Per-solve phase times (FCMP_FLAG_PHASE_TIMES): while a SolveTimes is
+// installed on the calling thread, every ProfScope also records a pair of
+// events for it.
+struct SolveTimes {
+  struct Rec { int phase; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  ~SolveTimes();
+};
+// RAII installation on the calling thread (nullptr: nothing installed).
+class SolveTimesScope {
+ public:
+  explicit SolveTimesScope(SolveTimes* s);
+  ~SolveTimesScope();
+  SolveTimesScope(const SolveTimesScope&) = delete;
+  SolveTimesScope& operator=(const SolveTimesScope&) = delete;
+
+ private:
+  SolveTimes* prev_;
+};
+// Synchronises the recorded events and sums them per phase (ms[FCMP_NPHASE]).
+int solve_times_read(SolveTimes& s, double* ms);
+
 // RAII phase timer: records hipEvents around a launch sequence when profiling
-// is enabled (fcmp_profile_enable); no-op otherwise.
+// is enabled (fcmp_profile_enable) or a SolveTimes is installed; no-op
+// otherwise.
 class ProfScope {
  public:
   ProfScope(int phase, hipStream_t st);
@@ -140,6 +163,8 @@ class ProfScope {
   int phase_;
   hipStream_t st_;
   hipEvent_t a_ = nullptr;
+  hipEvent_t sa_ = nullptr;
+  SolveTimes* solve_ = nullptr;
 };
 bool prof_enabled();
 // Phase events are not recorded by this thread while suspended (graph capture).

@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
       }
     }
   }
-  double bkey = -1.0;
+  double bkey = -1.0, bkey2 = -1.0;
   int64_t bidx = -1;
   const uint32_t* excl = p.excl ? p.excl + (int64_t)inst * p.inst_excl : nullptr;
   Wd* hout = p.h ? (Wd*)p.h + (int64_t)inst * p.inst_h : nullptr;
@@ -109,14 +109,11 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
     const int64_t j = jb + (int64_t)u * F_THREADS;
     if (j < p.N) {
       if (hout) hout[j] = acc[u];
-      if (p.partial && (!excl || !bit_is_set(excl, j))) {
-        const double kk = vmag2(acc[u]);
-        if (sel_better(kk, j, bkey, bidx)) { bkey = kk; bidx = j; }
-      }
+      if (p.partial && (!excl || !bit_is_set(excl, j))) sel_add(vmag2(acc[u]), j, bkey, bidx, bkey2);
     }
   }
   if (p.partial) {
-    const Sel r = block_sel_reduce(bkey, bidx, red);
+    const Sel r = block_sel_reduce(bkey, bidx, bkey2, red);
     if (tid == 0) p.partial[(int64_t)inst * p.inst_part + blockIdx.x] = r;
   }
 }

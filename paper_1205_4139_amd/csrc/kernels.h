@@ -218,9 +218,10 @@ hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam
                            hipStream_t st);
 hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st);
 // Mv / Kv (nullable): per-instance counts, at most M / K; NULL: M / K for all.
+// res_tol2: a solve stops once ||r||^2 <= res_tol2 ||y||^2 (0: never)
 hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier,
                               int64_t inst_y, int ninst, hipStream_t st,
-                              const int32_t* Mv = nullptr);
+                              const int32_t* Mv = nullptr, double res_tol2 = 0.0);
 hipError_t launch_gather_ptr(int vk, const void* const* ptrs, const int32_t* idx, void* dst,
                              int64_t n, int64_t inst_idx, int64_t inst_dst, int ninst,
                              hipStream_t st, const int32_t* Mv = nullptr);

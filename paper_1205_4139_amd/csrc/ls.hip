@@ -164,13 +164,13 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
 
   // ---- step 3: reduce the per-workgroup partials
   const Sel* part = p.partial + (int64_t)inst * p.inst_part;
-  double bk = -1.0;
+  double bk = -1.0, bk2 = -1.0;
   int64_t bi = -1;
   for (int e = tid; e < p.npart; e += L_THREADS) {
     const Sel s = part[e];
-    if (s.idx >= 0 && sel_better(s.key, s.idx, bk, bi)) { bk = s.key; bi = s.idx; }
+    if (s.idx >= 0) sel_merge(s.key, s.idx, s.key2, bk, bi, bk2);
   }
-  const Sel best = block_sel_reduce(bk, bi, red);
+  const Sel best = block_sel_reduce(bk, bi, bk2, red);
   if (best.idx < 0 || !(best.key > 0.0)) {
     if (tid == 0) st->done = 1;
     return;
@@ -265,6 +265,9 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
     st->znorm2 += vmag2(zt);
     st->iterations = p.t;
     st->last_key = best.key;
+    st->min_gap = fmin(st->min_gap, sel_gap(best));
+    // optional early stop on the residual norm, ||r||^2 = ||y||^2 - ||z||^2
+    if (st->res_tol2 > 0.0 && st->ynorm2 - st->znorm2 <= st->res_tol2 * st->ynorm2) st->done = 1;
   }
   if (p.ord) tap_order_insert(p, inst, n, j);
 }
@@ -289,22 +292,25 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   // status, the first partials and the first selected columns
   const int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
   const Sel* part = p.partial + (int64_t)inst * p.inst_part;
-  const Sel s0 = tid < p.npart ? part[tid] : Sel{-1.0, -1};
+  const Sel s0 = tid < p.npart ? part[tid] : Sel{-1.0, -1, -1.0};
   const int32_t l0 = tid < n ? lam[tid] : 0;
   if (st->done) return;
-  if (p.Kv && p.t > p.Kv[inst]) {   // its K selections are made
+  if ((p.Kv && p.t > p.Kv[inst]) ||   // its K selections are made
+      (st->res_tol2 > 0.0 && st->ynorm2 - st->znorm2 <= st->res_tol2 * st->ynorm2)) {
+    // (or the residual met the tolerance after the previous update; every
+    // workgroup of this launch reads the same record and returns)
     if (gid == 0 && threadIdx.x == 0) st->done = 1;
     return;
   }
   Wd* g = (Wd*)smem_raw;
-  double bk = -1.0;
+  double bk = -1.0, bk2 = -1.0;
   int64_t bi = -1;
-  if (s0.idx >= 0) { bk = s0.key; bi = s0.idx; }
+  if (s0.idx >= 0) { bk = s0.key; bi = s0.idx; bk2 = s0.key2; }
   for (int e = tid + L_THREADS; e < p.npart; e += L_THREADS) {
     const Sel s = part[e];
-    if (s.idx >= 0 && sel_better(s.key, s.idx, bk, bi)) { bk = s.key; bi = s.idx; }
+    if (s.idx >= 0) sel_merge(s.key, s.idx, s.key2, bk, bi, bk2);
   }
-  const Sel best = block_sel_reduce(bk, bi, red);
+  const Sel best = block_sel_reduce(bk, bi, bk2, red);
   if (best.idx < 0 || !(best.key > 0.0)) {
     if (gid == 0 && tid == 0) st->done = 1;
     return;
@@ -313,6 +319,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   if (gid == 0 && tid == 0) {
     st->cur_j = (int32_t)j;
     st->last_key = best.key;
+    st->min_gap = fmin(st->min_gap, sel_gap(best));
   }
   const uint32_t mask = (uint32_t)p.N - 1u;
   const Wd* c64 = (const Wd*)p.c64 + (int64_t)inst * p.inst_c;

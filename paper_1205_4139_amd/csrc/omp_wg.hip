@@ -145,20 +145,18 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
   const double inv_sqrt_n = 1.0 / sqrt((double)N);
   for (int e = tid; e < (N + 31) / 32; e += WG_THREADS) s.excl[e] = 0u;
   __syncthreads();
-  double znorm2 = 0.0;
+  double znorm2 = 0.0, min_gap = __builtin_inf();
+  const double ynorm2 = stat->ynorm2, res_tol2 = stat->res_tol2;
   int iters = 0;
   bool numeric = false;
   V* tile = (V*)s.tile;
   for (int t = 1; t <= K; ++t) {
-    double bk = -1.0;
+    double bk = -1.0, bk2 = -1.0;
     int64_t bi = -1;
     const bool fast = d.method == FCMP_CORR_FAST ||
                       (d.method == FCMP_CORR_ADAPTIVE && t <= d.switch_t);
     if (t == 1) {
-      for (int j = tid; j < N; j += WG_THREADS) {
-        const double kk = vmag2(h0[j]);
-        if (sel_better(kk, j, bk, bi)) { bk = kk; bi = j; }
-      }
+      for (int j = tid; j < N; j += WG_THREADS) sel_add(vmag2(h0[j]), (int64_t)j, bk, bi, bk2);
     } else if (fast) {
       // eq. (kernelsumOMP): h = h_0 - sum_tau x_tau P_{lam_tau} c, FP64 accumulation
       for (int j0 = tid; j0 < N; j0 += WG_THREADS * 4) {
@@ -186,10 +184,8 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int j = j0 + u * WG_THREADS;
-          if (j < N && !((s.excl[j >> 5] >> (j & 31)) & 1u)) {
-            const double kk = vmag2(acc[u]);
-            if (sel_better(kk, j, bk, bi)) { bk = kk; bi = j; }
-          }
+          if (j < N && !((s.excl[j >> 5] >> (j & 31)) & 1u))
+            sel_add(vmag2(acc[u]), (int64_t)j, bk, bi, bk2);
         }
       }
     } else {
@@ -237,17 +233,19 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
       lds_fft<F, false>(tile, N, logN, 1, 0, stage_tw<V>(p));
       for (int j = tid; j < N; j += WG_THREADS) {
         if ((s.excl[j >> 5] >> (j & 31)) & 1u) continue;
-        const double kk2 = vmag2(vscale(tile[lds_addr(j)], inv_sqrt_n));
-        if (sel_better(kk2, j, bk, bi)) { bk = kk2; bi = j; }
+        sel_add(vmag2(vscale(tile[lds_addr(j)], inv_sqrt_n)), (int64_t)j, bk, bi, bk2);
       }
     }
-    const Sel best = block_sel_reduce(bk, bi, s.red);
+    const Sel best = block_sel_reduce(bk, bi, bk2, s.red);
     if (best.idx < 0 || !(best.key > 0.0)) break;
+    min_gap = fmin(min_gap, sel_gap(best));
     if (!wg_ls<F>(d, base, s, t, (uint32_t)best.idx, znorm2)) {
       numeric = true;
       break;
     }
     iters = t;
+    // optional early stop on the residual norm, ||r||^2 = ||y||^2 - ||z||^2
+    if (res_tol2 > 0.0 && ynorm2 - znorm2 <= res_tol2 * ynorm2) break;
   }
   // results
   const Wd* xr = (const Wd*)(base + d.off_x);
@@ -261,6 +259,7 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
     stat->iterations = iters;
     stat->numeric = numeric ? 1 : 0;
     stat->znorm2 = znorm2;
+    stat->min_gap = min_gap;
     stat->t_done = (double)(wall_clock64() - *p.t0);
     stat->done = 1;
   }

@@ -281,15 +281,25 @@ static int upload_ptrs(fcmp_plan& P, const void* const* y, int32_t* const* sup, 
   return FCMP_OK;
 }
 
-int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats) {
+void stats_phases(fcmp_stats& s, const double* pms) {
+  s.ms_corr = (float)(pms[FCMP_PHASE_H0] + pms[FCMP_PHASE_CORR] + pms[FCMP_PHASE_FAST]);
+  s.ms_select = (float)pms[FCMP_PHASE_SELECT];
+  s.ms_ls = (float)pms[FCMP_PHASE_LS];
+  s.ms_resid = (float)pms[FCMP_PHASE_RESID];
+}
+
+int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats, const double* pms) {
   int worst = FCMP_OK;
   for (int64_t b = 0; b < n; ++b) {
+    stats[b] = fcmp_stats{};
     stats[b].iterations = hs[b].iterations;
-    stats[b].status = hs[b].numeric ? FCMP_E_NUMERIC : FCMP_OK;
+    stats[b].status_detail = hs[b].numeric ? FCMP_E_NUMERIC : FCMP_OK;
     const double r2 = hs[b].ynorm2 - hs[b].znorm2;
     stats[b].res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
+    stats[b].min_gap = hs[b].min_gap;
+    if (pms) stats_phases(stats[b], pms);
     stats[b].ms_total = ms;
-    if (stats[b].status != FCMP_OK) worst = stats[b].status;
+    if (stats[b].status_detail != FCMP_OK) worst = stats[b].status_detail;
   }
   if (worst != FCMP_OK) return set_error(worst, "Cholesky breakdown in at least one instance");
   return FCMP_OK;
@@ -313,7 +323,8 @@ static int plan_enqueue_prefix(fcmp_plan& P, const fcmp_options& opt, hipStream_
     HIP_TRY(launch_fill_u32(P.excl, 0u, P.n * P.sE, st));
     HIP_TRY(launch_gather_ptr(P.wk, (const void* const*)P.dptrs, P.perm, P.y_ent, M, P.sM, P.sM,
                               n, st, P.Mv));
-    HIP_TRY(launch_init_status(P.status, P.y_ent, M, F, P.sM, n, st, P.Mv));
+    HIP_TRY(launch_init_status(P.status, P.y_ent, M, F, P.sM, n, st, P.Mv,
+                               opt.res_tol * opt.res_tol));
   }
   const double inv_sqrt_n = 1.0 / std::sqrt((double)N);
   {
@@ -524,6 +535,11 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
   int rc = upload_ptrs(P, y, sup, xo, st);
   if (rc) return rc;
   const int n = (int)P.n;
+  // per-solve phase times: events around every phase of this solve
+  SolveTimes stm;
+  const bool phase_times = stats && timed && (opt.flags & FCMP_FLAG_PHASE_TIMES);
+  SolveTimesScope stm_scope(phase_times ? &stm : nullptr);
+  double pms[FCMP_NPHASE] = {0.0};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (stats && timed) {
     HIP_TRY(hipEventCreate(&e0));
@@ -539,6 +555,11 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
     rc = plan_enqueue_prefix(P, opt, st);
     if (!rc) rc = plan_solve_set(P, opt, (int32_t* const*)sup, xo, stats, st);
     drop_events();
+    if (phase_times && (!rc || rc == FCMP_E_NUMERIC)) {
+      const int prc = solve_times_read(stm, pms);
+      if (prc) return prc;
+      for (int64_t b = 0; b < P.n; ++b) stats_phases(stats[b], pms);
+    }
     return rc;
   }
   if ((rc = plan_enqueue(P, opt, st))) {
@@ -555,7 +576,11 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
       return set_error(FCMP_E_DEVICE, std::string("plan solve: ") + hipGetErrorString(e));
     std::vector<Status> hs((size_t)n);
     HIP_TRY(hipMemcpy(hs.data(), P.status, n * sizeof(Status), hipMemcpyDeviceToHost));
-    return plan_stats(n, hs.data(), ms, stats);
+    if (phase_times) {
+      const int prc = solve_times_read(stm, pms);
+      if (prc) return prc;
+    }
+    return plan_stats(n, hs.data(), ms, stats, phase_times ? pms : nullptr);
   }
   return FCMP_OK;
 }

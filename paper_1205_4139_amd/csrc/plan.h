@@ -103,7 +103,10 @@ RCParams rcorr_geometry(const fcmp_plan& P);
 int rcorr_threads(const RCParams& q);
 // Fills stats from host copies of the status records; FCMP_E_NUMERIC when any
 // instance broke down.
-int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats);
+int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats,
+               const double* phase_ms = nullptr);
+// Per-solve phase times (ms per FCMP_PHASE_*) into the stats fields.
+void stats_phases(fcmp_stats& s, const double* phase_ms);
 // SP / CoSaMP for every instance of the plan (after h_0 is in place)
 int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, void* const* xo,
                    fcmp_stats* stats, hipStream_t st);

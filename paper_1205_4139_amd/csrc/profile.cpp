@@ -18,6 +18,7 @@ std::vector<hipEvent_t> g_pool;
 double g_ms[FCMP_NPHASE];
 int64_t g_n[FCMP_NPHASE];
 thread_local int t_suspend = 0;   // > 0 while this thread captures a graph
+thread_local SolveTimes* t_solve = nullptr;
 
 hipEvent_t take_event() {
   if (!g_pool.empty()) {
@@ -38,8 +39,37 @@ bool prof_enabled() {
 
 void prof_suspend(bool on) { t_suspend += on ? 1 : -1; }
 
+SolveTimes::~SolveTimes() {
+  for (const Rec& r : recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+}
+
+SolveTimesScope::SolveTimesScope(SolveTimes* s) : prev_(t_solve) { t_solve = s; }
+SolveTimesScope::~SolveTimesScope() { t_solve = prev_; }
+
+int solve_times_read(SolveTimes& s, double* ms) {
+  for (int p = 0; p < FCMP_NPHASE; ++p) ms[p] = 0.0;
+  for (const SolveTimes::Rec& r : s.recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+      return set_error(FCMP_E_DEVICE, "phase event query failed");
+    ms[r.phase] += t;
+  }
+  return FCMP_OK;
+}
+
 ProfScope::ProfScope(int phase, hipStream_t st) : phase_(phase), st_(st) {
   if (t_suspend > 0) return;
+  if (t_solve) {
+    if (hipEventCreate(&sa_) == hipSuccess && hipEventRecord(sa_, st_) == hipSuccess) {
+      solve_ = t_solve;
+    } else if (sa_) {
+      (void)hipEventDestroy(sa_);
+      sa_ = nullptr;
+    }
+  }
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
   a_ = take_event();
@@ -50,6 +80,15 @@ ProfScope::ProfScope(int phase, hipStream_t st) : phase_(phase), st_(st) {
 }
 
 ProfScope::~ProfScope() {
+  if (solve_) {
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st_) == hipSuccess) {
+      solve_->recs.push_back(SolveTimes::Rec{phase_, sa_, b});
+    } else {
+      (void)hipEventDestroy(sa_);
+      if (b) (void)hipEventDestroy(b);
+    }
+  }
   if (!a_) return;
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t b = take_event();

@@ -275,13 +275,15 @@ int run_wave(fcmp_server* S, std::vector<Req*>& w, bool small, char* base, size_
     const size_t i = (size_t)order[q];
     r->sup.assign((const int32_t*)(stg.p + os[i]), (const int32_t*)(stg.p + os[i]) + r->prob.K);
     r->x.assign(stg.p + ox[i], stg.p + ox[i] + (size_t)r->prob.K * r->wbytes());
+    r->stats = fcmp_stats{};
     r->stats.iterations = hs[q].iterations;
-    r->stats.status = hs[q].numeric ? FCMP_E_NUMERIC : FCMP_OK;
+    r->stats.status_detail = hs[q].numeric ? FCMP_E_NUMERIC : FCMP_OK;
+    r->stats.min_gap = hs[q].min_gap;
     const double r2 = hs[q].ynorm2 - hs[q].znorm2;
     r->stats.res_norm = r2 > 0 ? std::sqrt(r2) : 0.0;
     r->stats.ms_total = small ? hs[q].t_done / (double)khz : t - r->times.t_launch;
     r->times.t_done = t;
-    r->rc = r->stats.status;
+    r->rc = r->stats.status_detail;
   }
   return FCMP_OK;
 }

@@ -17,6 +17,7 @@
 // Selection ties go to the lowest index; every support is kept ascending.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <vector>
 
 #include "plan.h"
@@ -151,7 +152,13 @@ int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, v
   const int K = (int)P.shape.K;
   const int N = (int)P.shape.N;
   const int max_iter = opt.max_iter > 0 ? opt.max_iter : 50;
+  const double rt2 = opt.res_tol * opt.res_tol;   // stop once ||r||^2 <= rt2 ||y||^2
   const size_t wb = vbytes(P.wk);
+  // top-K selections, timed as their own phase
+  auto topk = [&](const void* v, int kind, int n, const uint32_t* ex, int k, int32_t* out) {
+    ProfScope ps(FCMP_PHASE_SELECT, st);
+    return launch_topk(v, kind, n, ex, k, P.tkws, out, st);
+  };
   int worst = FCMP_OK;
   for (int64_t b = 0; b < P.n; ++b) {
     const Inst I = inst_view(P, b);
@@ -170,22 +177,22 @@ int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, v
     // (Ta, xa) and (Tc, xb); Tb holds merged supports, Td selected positions,
     // xc the fit on the merged support
     if (opt.algorithm == FCMP_SP) {
-      HIP_TRY(launch_topk(I.h0, P.wk, N, nullptr, K, P.tkws, dT, st));
+      HIP_TRY(topk(I.h0, P.wk, N, nullptr, K, dT));
       if ((rc = dense_ls(P, I, dT, K, dx, st))) return rc;
       if ((rc = resid_norm2(P, I, dT, dx, K, ynorm2, st, &rn2))) return rc;
       if ((rc = to_host(T, dT, K, st))) return rc;
-      while (iters < max_iter) {
+      while (iters < max_iter && !(rt2 > 0.0 && rn2 <= rt2 * ynorm2)) {
         ++iters;
         int hk;
         if ((rc = correlate_set(P, I, fast, dT, dx, K, st, &hk))) return rc;
         HIP_TRY(launch_set_bits(P.excl, P.sE, dT, K, st));
-        HIP_TRY(launch_topk(P.hbuf, hk, N, P.excl, K, P.tkws, P.Tb, st));
+        HIP_TRY(topk(P.hbuf, hk, N, P.excl, K, P.Tb));
         if ((rc = to_host(extra, P.Tb, K, st))) return rc;
         const std::vector<int32_t> Tt = merge_sorted(T, extra);
         const int st_n = (int)Tt.size();
         if ((rc = to_dev(P.Tb, Tt, st))) return rc;
         if ((rc = dense_ls(P, I, P.Tb, st_n, P.xc, st))) return rc;
-        HIP_TRY(launch_topk(P.xc, P.wk, st_n, nullptr, K, P.tkws, P.Td, st));   // positions in Tt
+        HIP_TRY(topk(P.xc, P.wk, st_n, nullptr, K, P.Td));   // positions in Tt
         std::vector<int32_t> keep;
         if ((rc = to_host(keep, P.Td, K, st))) return rc;
         Tn.resize(K);
@@ -216,13 +223,13 @@ int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, v
           if ((rc = correlate_set(P, I, fast, dS, da, (int)S.size(), st, &uk))) return rc;
           u = P.hbuf;
         }
-        HIP_TRY(launch_topk(u, uk, N, nullptr, 2 * K, P.tkws, P.Tb, st));
+        HIP_TRY(topk(u, uk, N, nullptr, 2 * K, P.Tb));
         if ((rc = to_host(extra, P.Tb, 2 * K, st))) return rc;
         const std::vector<int32_t> Tt = merge_sorted(extra, S);
         const int tn = (int)Tt.size();
         if ((rc = to_dev(P.Tb, Tt, st))) return rc;
         if ((rc = dense_ls(P, I, P.Tb, tn, P.xc, st))) return rc;
-        HIP_TRY(launch_topk(P.xc, P.wk, tn, nullptr, K, P.tkws, P.Td, st));
+        HIP_TRY(topk(P.xc, P.wk, tn, nullptr, K, P.Td));
         std::vector<int32_t> keep;
         if ((rc = to_host(keep, P.Td, K, st))) return rc;
         std::vector<int32_t> Sn(K);
@@ -236,7 +243,7 @@ int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, v
         S = Sn; dS = dSn; da = dan;
         double vn2;
         if ((rc = resid_norm2(P, I, dS, da, K, ynorm2, st, &vn2))) return rc;
-        if (same || vn2 <= 1e-24 * ynorm2) break;
+        if (same || vn2 <= 1e-24 * ynorm2 || (rt2 > 0.0 && vn2 <= rt2 * ynorm2)) break;
       }
       // final refit on the support
       void* dxf = P.xc;
@@ -253,8 +260,10 @@ int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, v
     HIP_TRY(hipStreamSynchronize(st));
     if (bad) worst = FCMP_E_NUMERIC;
     if (stats) {
+      stats[b] = fcmp_stats{};
       stats[b].iterations = iters;
-      stats[b].status = bad ? FCMP_E_NUMERIC : FCMP_OK;
+      stats[b].status_detail = bad ? FCMP_E_NUMERIC : FCMP_OK;
+      stats[b].min_gap = std::numeric_limits<double>::quiet_NaN();
       stats[b].res_norm = rn2 > 0 ? std::sqrt(rn2) : 0.0;
       stats[b].ms_total = 0.0;
     }

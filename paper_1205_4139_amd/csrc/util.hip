@@ -104,13 +104,13 @@ hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam
 
 __global__ void reduce_sel_kernel(const Sel* partial, int n, Sel* out) {
   __shared__ Sel red[16];
-  double bk = -1.0;
+  double bk = -1.0, bk2 = -1.0;
   int64_t bi = -1;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const Sel s = partial[e];
-    if (s.idx >= 0 && sel_better(s.key, s.idx, bk, bi)) { bk = s.key; bi = s.idx; }
+    if (s.idx >= 0) sel_merge(s.key, s.idx, s.key2, bk, bi, bk2);
   }
-  const Sel r = block_sel_reduce(bk, bi, red);
+  const Sel r = block_sel_reduce(bk, bi, bk2, red);
   if (threadIdx.x == 0) *out = r;
 }
 
@@ -121,7 +121,7 @@ hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st
 
 // status[inst] = {0...}, ynorm2 = ||y||^2 (one workgroup per instance)
 __global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, int64_t inst_y,
-                                   const int32_t* Mv, int per_row) {
+                                   const int32_t* Mv, int per_row, double res_tol2) {
   __shared__ double dred[16];
   const int inst = blockIdx.x;
   if (Mv) nreal = (int64_t)Mv[inst] * per_row;
@@ -133,16 +133,17 @@ __global__ void init_status_kernel(Status* st, const double* y, int64_t nreal, i
     Status z;
     z.done = 0; z.numeric = 0; z.iterations = 0; z.cur_j = -1;
     z.znorm2 = 0.0; z.ynorm2 = s; z.last_key = 0.0; z.t_done = 0.0;
+    z.min_gap = __builtin_inf(); z.res_tol2 = res_tol2;
     st[inst] = z;
   }
 }
 
 hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier, int64_t inst_y,
-                              int ninst, hipStream_t st, const int32_t* Mv) {
+                              int ninst, hipStream_t st, const int32_t* Mv, double res_tol2) {
   const int64_t nreal = fourier ? 2 * (int64_t)M : M;
   const int64_t istride = fourier ? 2 * inst_y : inst_y;
   hipLaunchKernelGGL(init_status_kernel, dim3(ninst), dim3(256), 0, st, st_dev,
-                     (const double*)y, nreal, istride, Mv, fourier ? 2 : 1);
+                     (const double*)y, nreal, istride, Mv, fourier ? 2 : 1, res_tol2);
   return hipGetLastError();
 }
 

@@ -227,8 +227,8 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
   // ---- store / identify (keys |v|^2 unscaled in the transform precision;
   // the winner's key is scaled once at the end)
   using KT = typename KeyOf<V>::T;
-  KT bkey = (KT)-1;
-  int bidx = -1;
+  KT bkey = (KT)-1, bkey2 = (KT)-1;
+  int64_t bidx = -1;
   const bool store = p.out_kind >= 0 || p.out2_kind >= 0;
   const int out_ss = (int)p.out_ss, out_es = (int)p.out_es;
   for (int e = tid; e < tile_n; e += nt) {
@@ -265,15 +265,14 @@ __global__ void __launch_bounds__(256) xform_kernel(XParams p) {
         else if (p.excl_mode == 2) ex = (xw[j] >> ((s0 + c) & 31)) & 1u;
         else ex = bit_is_set(excl, o);
       }
-      if (!ex) {
-        const KT kk = kmag2(v);
-        if (kk > bkey || (kk == bkey && (unsigned)o < (unsigned)bidx)) { bkey = kk; bidx = o; }
-      }
+      if (!ex) sel_add(kmag2(v), (int64_t)o, bkey, bidx, bkey2);
     }
   }
   if (p.partial) {
-    const double key = bidx >= 0 ? (double)bkey * (p.scale * p.scale) : -1.0;
-    const Sel r = block_sel_reduce(key, (int64_t)bidx, red);
+    const double s2 = p.scale * p.scale;
+    const double key = bidx >= 0 ? (double)bkey * s2 : -1.0;
+    const double key2 = bkey2 >= (KT)0 ? (double)bkey2 * s2 : -1.0;
+    const Sel r = block_sel_reduce(key, bidx, key2, red);
     if (tid == 0) p.partial[(int64_t)inst * p.inst_part + g] = r;
   }
 }

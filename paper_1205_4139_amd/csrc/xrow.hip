@@ -144,20 +144,19 @@ __global__ void __launch_bounds__(256) xrow_kernel(XParams p) {
   // ---- identification over the lane's 16 outputs (keys |v|^2 unscaled in
   // the transform precision; the winner's key is scaled once)
   using KT = decltype(kmag2r(V()));
-  KT bkey = (KT)-1;
-  int bidx = -1;
+  KT bkey = (KT)-1, bkey2 = (KT)-1;
+  int64_t bidx = -1;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int j1 = j1base + j1step * r;
     const int o = FFT ? row + n2 * j1 : row * L + j1;
     const uint32_t xw = FFT ? xws[j1] : xws[(row - row0) * (L / 32) + (j1 >> 5)];
-    if (!((xw >> (o & 31)) & 1u)) {
-      const KT kk = kmag2r(s[r]);
-      if (kk > bkey || (kk == bkey && (unsigned)o < (unsigned)bidx)) { bkey = kk; bidx = o; }
-    }
+    if (!((xw >> (o & 31)) & 1u)) sel_add(kmag2r(s[r]), (int64_t)o, bkey, bidx, bkey2);
   }
-  const double key = bidx >= 0 ? (double)bkey * (p.scale * p.scale) : -1.0;
-  const Sel sel = block_sel_reduce(key, (int64_t)bidx, red);
+  const double s2 = p.scale * p.scale;
+  const double key = bidx >= 0 ? (double)bkey * s2 : -1.0;
+  const double key2 = bkey2 >= (KT)0 ? (double)bkey2 * s2 : -1.0;
+  const Sel sel = block_sel_reduce(key, bidx, key2, red);
   if (tid == 0) p.partial[(int64_t)inst * p.inst_part + blockIdx.x] = sel;
 }
 

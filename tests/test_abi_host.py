@@ -32,7 +32,7 @@ def test_header_symbols_exported(fc):
 
 
 def test_abi_version_and_status(fc):
-    assert fc.lib.fcmp_abi_version() == 1
+    assert fc.lib.fcmp_abi_version() == 2
     assert fc.lib.fcmp_status_str(0) == b"ok"
     assert fc.lib.fcmp_status_str(-2) == b"workspace too small"
 
@@ -110,7 +110,7 @@ def test_options_validation(fc):
         _q(fc, precision=5)
     p, om = fc.make_problem("H", 1024, 256, 16, np.arange(256) * 4)
     o = fc.make_options()
-    o.flags = 16   # no such flag
+    o.flags = 32   # no such flag
     n = ctypes.c_size_t(0)
     assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID
 
@@ -168,3 +168,46 @@ def test_adaptive_switch_model_and_cache(fc, tmp_path):
         fc.autotune_load(tmp_path / "empty.txt")
     with pytest.raises(fc.FcmpError, match="power of two"):
         fc.adaptive_switch("F", 1000, "fp32")
+
+
+def _struct_fields(name):
+    """Member names of a typedef struct in the header, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            out += [v.strip().lstrip("*") for v in decl.split(None, 1)[1].split(",")]
+    return out
+
+
+def test_stats_layout_matches_header(fc):
+    """fcmp_stats: the binding's field order is the header's, and its size is
+    what the C layout gives (int32 x 2, double x 2, float x 4, double)."""
+    assert [f[0] for f in fc.Stats._fields_] == _struct_fields("fcmp_stats")
+    assert ctypes.sizeof(fc.Stats) == 48
+    assert fc.Stats.min_gap.offset == 16 and fc.Stats.ms_total.offset == 40
+    assert [f[0] for f in fc.Options._fields_] == _struct_fields("fcmp_options")
+
+
+@pytest.mark.parametrize("tol,ok", [(0.0, True), (0.3, True), (1e-12, True), (-1e-3, False),
+                                    (1.0, False), (float("nan"), False)])
+def test_res_tol_validation(fc, tol, ok):
+    p, om = fc.make_problem("H", 1024, 256, 16, np.arange(256) * 4)
+    o = fc.make_options(res_tol=tol)
+    n = ctypes.c_size_t(0)
+    rc = fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n))
+    if ok:
+        assert rc == 0 and n.value > 0
+    else:
+        assert rc == fc.E_INVALID and b"res_tol" in fc.lib.fcmp_last_error()
+
+
+def test_phase_times_flag_accepted(fc):
+    p, om = fc.make_problem("H", 1024, 256, 16, np.arange(256) * 4)
+    n = ctypes.c_size_t(0)
+    o = fc.make_options(flags=fc.FLAG_PHASE_TIMES)
+    assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == 0
+    o = fc.make_options(flags=64)
+    assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID

@@ -47,7 +47,7 @@ def test_fourier_65536_lockstep_plan_256(fc, method):
     plan = fc.Plan("F", N, M, K, [i.omega for i in insts], precision="fp32", method=method)
     sup, x, stats = plan.solve(ys, method=method, stats=True)
     sup, x = to_np(sup).copy(), to_np(x).copy()
-    assert all(s.status == 0 and s.iterations == K for s in stats)
+    assert all(s.status_detail == 0 and s.iterations == K for s in stats)
     assert list(sup[0]) == ref["support"]
     xr = np.array(ref["x_re"]) + 1j * np.array(ref["x_im"])
     assert np.linalg.norm(x[0] - xr) <= 1e-10 * np.linalg.norm(xr)
@@ -83,7 +83,7 @@ def test_uneven_4096_batch_plan(fc):
     ys = [to_dev(oracle.problem.instance_measure(i, tier="transform")) for i in insts]
     bp = fc.BatchPlan([(i.cls, i.N, i.M, i.K, i.omega) for i in insts], precision="fp32")
     sup, x, st = bp.solve(ys, stats=True)
-    assert all(st[k].status == 0 and st[k].iterations == insts[k].K for k in range(len(insts)))
+    assert all(st[k].status_detail == 0 and st[k].iterations == insts[k].K for k in range(len(insts)))
     rng = np.random.default_rng(77)
     small = [k for k in range(len(insts)) if insts[k].N <= 4096]
     checked = 0

@@ -61,7 +61,7 @@ def test_omp_parity(fc, case, method, precision):
                        method=method, precision=precision)
         sup = to_np(res.support)
         x = to_np(res.x)
-        assert res.stats.status == 0
+        assert res.stats.status_detail == 0
         assert res.stats.iterations == inst.K
         assert list(sup) == list(ref.support)
         assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
@@ -116,3 +116,61 @@ def test_omp_more_taps_than_one_staged_chunk(fc, cls):
     res = fc.solve(cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y), precision="fp64")
     assert list(to_np(res.support)) == list(ref.support)
     assert np.linalg.norm(to_np(res.x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", [CASES[0], CASES[3], CASES[5]], ids=lambda c: f"{c[0]}{c[1]}")
+def test_min_gap_matches_oracle(fc, case, precision):
+    """stats.min_gap is the smallest relative identification gap of the solve.
+    The oracle normalises by the largest |h| over all columns, the library by
+    the winner's |h|; selected columns have |h| = 0 in exact arithmetic, so the
+    two agree up to the correlation error (a few tol)."""
+    for method in ("conventional", "fast"):
+        inst, y, ref = _reference(case, 7000)
+        res = fc.solve(inst.cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y), method=method,
+                       precision=precision)
+        assert abs(res.stats.min_gap - certify.min_gap(ref)) <= 3 * TOL[precision] + 1e-12
+
+
+@pytest.mark.parametrize("method", ["conventional", "fast"])
+@pytest.mark.parametrize("cls,N,M", [("H", 1024, 256), ("F", 65536, 16384)])
+def test_res_tol_stops_with_the_oracle(fc, cls, N, M, method):
+    """Noiseless K0-sparse x, OMP asked for 3 K0 selections with
+    res_tol = 1e-6: the library stops where the oracle does (after the K0
+    planted columns), with the same selection order and x.  The persistent
+    batch kernel (N = 1024 through fcmp_batch_solve) stops the same way."""
+    K0 = 12
+    inst = instancegen.draw_instance(cls, N, M, K0, "pm_u12", None, 7300)
+    y = oracle.problem.instance_measure(inst, tier="transform")
+    ref = oracle.omp(oracle.make_operator(cls, N, inst.omega), y, 3 * K0, res_tol=1e-6)
+    assert ref.iterations == K0
+    res = fc.solve(cls, N, M, 3 * K0, inst.omega, to_dev(y), method=method, precision="fp64",
+                   res_tol=1e-6)
+    assert res.stats.iterations == K0
+    sup = to_np(res.support)
+    assert list(sup[:K0]) == list(ref.support) and np.all(sup[K0:] == -1)
+    assert np.linalg.norm(to_np(res.x)[:K0] - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    assert res.stats.res_norm <= 1e-6 * np.linalg.norm(y)
+    if N <= 4096:
+        sups, xs, st = fc.batch_solve([(cls, N, M, 3 * K0, inst.omega)], [to_dev(y)],
+                                      method=method, precision="fp64", res_tol=1e-6)
+        assert st[0].iterations == K0
+        assert list(to_np(sups[0])[:K0]) == list(ref.support)
+
+
+def test_phase_times_per_solve(fc):
+    """FCMP_FLAG_PHASE_TIMES: the solve reports its own phase times, which
+    are positive where the phase ran and together stay within the solve's
+    device time."""
+    inst, y, ref = _reference(CASES[5], 7000)
+    res = fc.solve(inst.cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y), precision="fp32",
+                   flags=fc.FLAG_PHASE_TIMES)
+    s = res.stats
+    assert s.ms_corr > 0 and s.ms_ls > 0 and s.ms_select == 0
+    assert s.ms_corr + s.ms_ls + s.ms_resid <= 1.05 * s.ms_total
+    plain = fc.solve(inst.cls, inst.N, inst.M, inst.K, inst.omega, to_dev(y), precision="fp32")
+    assert plain.stats.ms_corr == 0 and plain.stats.ms_ls == 0
+    assert list(to_np(plain.support)) == list(to_np(res.support))

@@ -49,7 +49,7 @@ def test_set_algorithm_parity(fc, case, alg, method, precision):
                    method=method, precision=precision)
     sup = to_np(res.support)
     x = to_np(res.x)
-    assert res.stats.status == 0
+    assert res.stats.status_detail == 0
     assert list(sup) == list(ref.support)
     assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
 
@@ -87,3 +87,19 @@ def test_full_size_hadamard_exact_recovery(fc, alg, method):
     x = to_np(res.x)
     want = inst.x_dense()[sup]
     assert np.linalg.norm(x - want) <= 1e-10 * np.linalg.norm(want)
+
+
+@pytest.mark.parametrize("alg", ["sp", "cosamp"])
+def test_set_pursuit_res_tol_and_select_time(fc, alg):
+    """SP / CoSaMP with res_tol: the loop stops where the oracle's does, with
+    the same support and x; FCMP_FLAG_PHASE_TIMES reports the top-K time."""
+    inst = instancegen.draw_instance("H", 4096, 1024, 20, "pm_u12", None, 7400)
+    y = oracle.problem.instance_measure(inst, tier="transform")
+    op = oracle.make_operator("H", 4096, inst.omega)
+    ref = getattr(oracle, alg)(op, y, 20, res_tol=1e-6)
+    res = fc.solve("H", 4096, 1024, 20, inst.omega, to_dev(y), algorithm=alg, precision="fp64",
+                   res_tol=1e-6, flags=fc.FLAG_PHASE_TIMES)
+    assert res.stats.iterations == ref.iterations
+    assert list(to_np(res.support)) == list(ref.support)
+    assert np.linalg.norm(to_np(res.x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    assert res.stats.ms_select > 0 and np.isnan(res.stats.min_gap)

@@ -147,3 +147,59 @@ def test_measure_snr_exact():
     clean = oracle.problem.clean_measure("F", 512, inst.omega, inst.x_dense())
     snr = 20 * np.log10(np.linalg.norm(clean) / np.linalg.norm(y - clean))
     assert abs(snr - 30.0) < 1e-9
+
+
+@pytest.mark.parametrize("cls", ["F", "H"])
+@pytest.mark.parametrize("method", ["conventional", "fast"])
+def test_omp_residual_rule_stops_at_the_true_sparsity(cls, method):
+    """Noiseless K0-sparse x with OMP asked for 3 K0 selections: after the K0
+    planted columns the residual is 0 up to rounding, so the residual rule
+    (||r|| <= res_tol ||y||) ends the solve there with x exact; without the
+    rule OMP makes all 3 K0 selections."""
+    K0 = 8
+    inst, y = _inst(cls, 512, 160, K0, "pm_u12", None, 130)
+    op = oracle.make_operator(cls, inst.N, inst.omega)
+    r = oracle.omp(op, y, 3 * K0, method, res_tol=1e-9)
+    assert r.iterations == K0
+    assert set(r.support) == set(inst.support)
+    assert np.allclose(r.x, inst.x_dense()[r.support], rtol=0, atol=1e-12)
+    assert r.res_norm <= 1e-9 * np.linalg.norm(y)
+    full = oracle.omp(op, y, 3 * K0, method)
+    assert full.iterations == 3 * K0
+    assert list(full.support[:K0]) == list(r.support)
+
+
+def test_omp_residual_rule_threshold_sides():
+    """The rule compares the residual after each selection with res_tol ||y||:
+    M = N (unitary Phi) and x with magnitudes 8, 4, 2, 1 on four columns, so
+    after t selections ||r||^2 is the sum of the remaining squared magnitudes
+    (closed form).  A tolerance just above that ratio at t = 2 stops at 2, one
+    just below it at 3."""
+    N = 32
+    om = np.arange(N, dtype=np.int32)
+    op = un.make_operator("H", N, om, "dense")
+    x = np.zeros(N)
+    x[[3, 9, 17, 30]] = [8.0, -4.0, 2.0, 1.0]
+    y = op.forward(x)
+    ratio2 = np.sqrt(2.0 ** 2 + 1.0) / np.sqrt(64 + 16 + 4 + 1)
+    assert oracle.omp(op, y, 4, res_tol=ratio2 * (1 + 1e-9)).iterations == 2
+    assert oracle.omp(op, y, 4, res_tol=ratio2 * (1 - 1e-9)).iterations == 3
+
+
+@pytest.mark.parametrize("alg", ["sp", "cosamp"])
+def test_set_pursuit_residual_rule(alg):
+    """M = N: the first fit is already exact, so with the residual rule SP
+    ends before its loop (0 iterations) and CoSaMP after its first; both
+    return the planted support and x."""
+    N, K = 64, 5
+    om = np.arange(N, dtype=np.int32)
+    op = un.make_operator("F", N, om, "dense")
+    rng = np.random.default_rng(31)
+    supp = np.sort(rng.choice(N, K, replace=False))
+    x = np.zeros(N, dtype=complex)
+    x[supp] = 1.5 + rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    y = op.forward(x)
+    r = getattr(oracle, alg)(op, y, K, res_tol=1e-10)
+    assert r.iterations == (0 if alg == "sp" else 1)
+    assert list(r.support) == list(supp)
+    assert np.allclose(r.x, x[supp], rtol=0, atol=1e-12)

@@ -38,7 +38,7 @@ def test_noalloc_matches_solve(fc, seq):
         y = to_dev(oracle.problem.instance_measure(inst, tier="transform"))
         want = fc.solve(cls, N, M, K, inst.omega, y, method=method, precision=prec)
         got = fc.solve_noalloc(cls, N, M, K, inst.omega, y, method=method, precision=prec)
-        assert got.stats.status == 0 and got.stats.iterations == K
+        assert got.stats.status_detail == 0 and got.stats.iterations == K
         assert np.array_equal(to_np(got.support), to_np(want.support)), (k, cls, N)
         assert np.array_equal(to_np(got.x), to_np(want.x)), (k, cls, N)
         assert got.stats.iterations == want.stats.iterations

@@ -50,3 +50,29 @@ def test_stored_uneven_batch_solves_match_planted_signals():
         want = inst.x_dense()[sup]
         assert np.linalg.norm(x - want) <= 0.01 * np.linalg.norm(want)
         assert e["min_gap"] >= 2.5e-5
+
+
+HADAMARD = os.path.join(os.path.dirname(__file__), "golden",
+                        "hadamard_n1m_m131072_k1024_seed3000.json")
+
+
+def test_stored_hadamard_1m_solves_match_planted_signal():
+    """The stored oracle solves of partial Hadamard N = 2^20, M = 2^17,
+    K = 1024 (noiseless, +-U(1,2) values): OMP, SP and CoSaMP each return the
+    planted support with the planted values (noiseless exact recovery), and
+    the OMP gaps are certified at FP64."""
+    ref = json.load(open(HADAMARD))
+    inst = instancegen.draw_config("hadamard_n1m", ref["index"])
+    assert inst.seed == ref["seed"] and inst.N == 1 << 20 and inst.K == 1024
+    want_set = sorted(inst.support.tolist())
+    for alg in ("omp", "sp", "cosamp"):
+        e = ref[alg]
+        sup = np.array(e["support"])
+        assert sorted(sup.tolist()) == want_set
+        x = np.array(e["x"]["re"])
+        assert np.max(np.abs(x - inst.x_dense()[sup])) <= 1e-10
+    assert ref["sp"]["support"] == want_set and ref["cosamp"]["support"] == want_set
+    g = np.array(ref["omp"]["gaps"])
+    assert len(g) == 1024 and np.all(g > 0)
+    assert ref["omp"]["certified"]["fp64"] and not ref["omp"]["certified"]["fp32"]
+    assert abs(ref["omp"]["min_gap"] - g.min()) == 0.0

@@ -343,6 +343,22 @@ int fcmp_autotune_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
 int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
                   int32_t batch, const char* cache_path, void* ws_dev, size_t ws_bytes,
                   int32_t* switch_t, void* hip_stream);
+/* The measurement behind the autotuner, exposed: the device time of one
+ * fast (eq. (kernelsumOMP), t - 1 taps) and one conventional (residual and
+ * transform) correlation launch sequence of a lockstep plan of `batch`
+ * problems (class, N, M) at each iteration ts[i] (each >= 2 and <= M - 1),
+ * written to fast_ms[i] and conv_ms[i] (ms per launch sequence over the whole
+ * batch, mean of a few repetitions).  This is the per-iteration cost curve
+ * whose crossing is the adaptive strategy's switch (Sec. IV; Table I gives
+ * the flop-count version).  The workspace size comes from
+ * fcmp_corr_curve_query_workspace with tmax = max ts (host-only).  The call
+ * synchronises the stream. */
+int fcmp_corr_curve_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
+                                    int32_t corr_precision, int32_t batch, int32_t tmax,
+                                    size_t* bytes);
+int fcmp_corr_curve(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
+                    int32_t batch, const int32_t* ts, int32_t nt, void* ws_dev, size_t ws_bytes,
+                    float* fast_ms, float* conv_ms, void* hip_stream);
 /* Loads every valid entry of a cache file into the table (host-only);
  * FCMP_E_NOTFOUND when the file is missing or holds no valid entry. */
 int fcmp_autotune_load(const char* cache_path);
@@ -392,8 +408,9 @@ int fcmp_kernel_vector(const fcmp_problem* prob, int32_t precision,
  *          FP64; float32 | complex64 for FP32), aligned with omega
  * h_dev  : device (nullable), N values in the same precision
  * excl_dev: device (nullable), uint32[(N+31)/32] bitmap of excluded columns
- * sel_dev: device (nullable), 16 bytes {double |h|^2, int64 index} of the winner
- *          (index -1 when every column is excluded or h vanishes)          */
+ * sel_dev: device (nullable), 24 bytes {double |h|^2, int64 index, double
+ *          runner-up |h|^2} of the winner (index -1 when every column is
+ *          excluded or h vanishes; runner-up -1 when there is none)        */
 int fcmp_correlate_workspace(const fcmp_problem* prob, int32_t precision,
                              size_t* bytes);
 int fcmp_correlate(const fcmp_problem* prob, int32_t precision,

@@ -114,6 +114,11 @@ def _load():
         "fcmp_autotune": ([i32, i64, i64, i32, i32, ctypes.c_char_p, vp, sz,
                            ctypes.POINTER(i32), vp], ctypes.c_int),
         "fcmp_autotune_load": ([ctypes.c_char_p], ctypes.c_int),
+        "fcmp_corr_curve_query_workspace": ([i32, i64, i64, i32, i32, i32, ctypes.POINTER(sz)],
+                                            ctypes.c_int),
+        "fcmp_corr_curve": ([i32, i64, i64, i32, i32, ctypes.POINTER(i32), i32, vp, sz,
+                             ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), vp],
+                            ctypes.c_int),
         "fcmp_adaptive_switch": ([i32, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
                                  ctypes.c_int),
         "fcmp_server_footprint": ([P, O, ctypes.POINTER(sz)], ctypes.c_int),
@@ -267,7 +272,7 @@ def kernel_vector(cls, N, omega, precision="fp64", device="cuda"):
 
 def _sel_tensor(device):
     torch = _torch()
-    return torch.zeros(2, dtype=torch.float64, device=device)
+    return torch.zeros(3, dtype=torch.float64, device=device)   # {key, index, runner-up key}
 
 
 def decode_sel(sel) -> tuple:
@@ -576,6 +581,22 @@ def autotune(cls, N, M, precision="fp32", batch=8, cache_path=None, device="cuda
                              cache_path.encode() if cache_path else None, _ptr(ws), ws.numel(),
                              ctypes.byref(t), _stream()))
     return t.value
+
+
+def corr_curve(cls, N, M, ts, precision="fp32", batch=1, device="cuda"):
+    """Per-iteration device time (ms per launch sequence over the batch) of
+    the fast and the conventional correlation at each iteration t in ts."""
+    ts = [int(t) for t in ts]
+    nb = ctypes.c_size_t(0)
+    _check(lib.fcmp_corr_curve_query_workspace(CLASS[cls], int(N), int(M), PREC[precision],
+                                               int(batch), max(ts), ctypes.byref(nb)))
+    ws = _workspace(nb.value, device)
+    ta = (ctypes.c_int32 * len(ts))(*ts)
+    fa = (ctypes.c_float * len(ts))()
+    ca = (ctypes.c_float * len(ts))()
+    _check(lib.fcmp_corr_curve(CLASS[cls], int(N), int(M), PREC[precision], int(batch), ta,
+                               len(ts), _ptr(ws), ws.numel(), fa, ca, _stream()))
+    return list(fa), list(ca)
 
 
 def autotune_load(cache_path) -> None:

@@ -71,16 +71,94 @@ int fcmp_autotune_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
   return FCMP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// A lockstep plan of `batch` problems (class, N, M) laid out in the caller's
+// workspace with synthetic taps (distinct columns, odd stride; unit
+// coefficients) and y = 0, ready for single correlation launch sequences.
+struct CurveBench {
+  fcmp_plan P;
+  std::vector<int32_t> om, lam, hord, hbst;
+  std::vector<fcmp_problem> probs;
+  hipStream_t st = nullptr;
+  hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+  ~CurveBench() {
+    for (hipEvent_t ev : e)
+      if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+int curve_setup(CurveBench& C, int32_t cls, int64_t N, int64_t M, int32_t prec, int32_t batch,
+                int32_t tmax, void* ws_dev, size_t ws_bytes, hipStream_t st) {
+  fcmp_options opt;
+  int rc = tune_shape(cls, N, M, batch, tmax, C.om, C.probs, opt, prec);
+  if (rc) return rc;
+  fcmp_plan& P = C.P;
+  if ((rc = plan_init(P, batch, C.probs.data(), &opt))) return rc;
+  if (!ws_dev) return set_error(FCMP_E_INVALID, "workspace is NULL");
+  if (ws_bytes < P.total) return set_error(FCMP_E_WORKSPACE, "workspace too small");
+  C.st = st;
+  plan_layout(P, (char*)ws_dev);
+  if ((rc = plan_build(P, C.probs.data(), st))) return rc;
+  const bool F = cls == FCMP_FOURIER;
+  const size_t wb = F ? 16 : 8;
+  C.lam.assign((size_t)(batch * P.sK), 0);
+  std::vector<double> x((size_t)(batch * P.sK) * (wb / 8), 0.0);
+  for (int64_t b = 0; b < batch; ++b)
+    for (int64_t k = 0; k < P.shape.K; ++k) {
+      C.lam[(size_t)(b * P.sK + k)] = (int32_t)((k * 40503 + 17) & (N - 1));
+      x[(size_t)(b * P.sK + k) * (wb / 8)] = 1.0;
+    }
+  HIP_TRY(hipMemcpyAsync(P.lam, C.lam.data(), C.lam.size() * 4, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.x, x.data(), x.size() * 8, hipMemcpyHostToDevice, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)P.y_ent, 0u, (int64_t)(batch * P.sM * wb / 4), st));
+  HIP_TRY(launch_fill_u32(P.excl, 0u, batch * P.sE, st));
+  HIP_TRY(launch_fill_u32((uint32_t*)P.h0, 0u, (int64_t)(batch * P.sN * wb / 4), st));
+  HIP_TRY(launch_init_status(P.status, P.y_ent, (int)M, F, P.sM, batch, st));
+  for (hipEvent_t& ev : C.e) HIP_TRY(hipEventCreate(&ev));
+  // warm up both paths (the host copies of x must land before the vector dies)
+  int npart = 0;
+  if ((rc = plan_set_tap_order(P, C.lam.data(), 1, st, C.hord, C.hbst)) ||
+      (rc = plan_fast_corr(P, 2, &npart, st)) || (rc = plan_conv_corr(P, 2, &npart, st)))
+    return rc;
+  HIP_TRY(hipStreamSynchronize(st));
+  return FCMP_OK;
+}
+
+// Mean device time of one fast and one conventional correlation launch
+// sequence at iteration t (t - 1 taps), over kReps of each.
+int curve_point(CurveBench& C, int t, float* fast_ms, float* conv_ms) {
+  fcmp_plan& P = C.P;
+  hipStream_t st = C.st;
+  int npart = 0, rc;
+  if ((rc = plan_set_tap_order(P, C.lam.data(), t - 1, st, C.hord, C.hbst))) return rc;
+  HIP_TRY(hipEventRecord(C.e[0], st));
+  for (int r = 0; r < kReps; ++r)
+    if ((rc = plan_fast_corr(P, t, &npart, st))) return rc;
+  HIP_TRY(hipEventRecord(C.e[1], st));
+  for (int r = 0; r < kReps; ++r)
+    if ((rc = plan_conv_corr(P, t, &npart, st))) return rc;
+  HIP_TRY(hipEventRecord(C.e[2], st));
+  HIP_TRY(hipEventSynchronize(C.e[2]));
+  float a = 0.f, b = 0.f;
+  HIP_TRY(hipEventElapsedTime(&a, C.e[0], C.e[1]));
+  HIP_TRY(hipEventElapsedTime(&b, C.e[1], C.e[2]));
+  *fast_ms = a / kReps;
+  *conv_ms = b / kReps;
+  return FCMP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
                   int32_t batch, const char* cache_path, void* ws_dev, size_t ws_bytes,
                   int32_t* switch_t, void* hip_stream) {
   if (!switch_t) return set_error(FCMP_E_INVALID, "switch_t is NULL");
   const int tmax = model_switch_t(matrix_class, N) * 8 + 8;
-  std::vector<int32_t> om;
-  std::vector<fcmp_problem> probs;
-  fcmp_options opt;
-  int rc = tune_shape(matrix_class, N, M, batch, tmax, om, probs, opt, corr_precision);
-  if (rc) return rc;
   if (cache_path && fcmp_autotune_load(cache_path) == FCMP_OK) {
     int t = 0;
     if (tuned_switch(matrix_class, N, corr_precision, &t)) {
@@ -88,61 +166,17 @@ int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_preci
       return FCMP_OK;
     }
   }
-  fcmp_plan P;
-  if ((rc = plan_init(P, batch, probs.data(), &opt))) return rc;
-  if (!ws_dev) return set_error(FCMP_E_INVALID, "workspace is NULL");
-  if (ws_bytes < P.total) return set_error(FCMP_E_WORKSPACE, "workspace too small");
-  hipStream_t st = (hipStream_t)hip_stream;
-  plan_layout(P, (char*)ws_dev);
-  if ((rc = plan_build(P, probs.data(), st))) return rc;
-  // taps: distinct columns (odd stride), unit coefficients; y = 0
-  const bool F = matrix_class == FCMP_FOURIER;
-  const size_t wb = F ? 16 : 8;
-  std::vector<int32_t> lam((size_t)(batch * P.sK), 0);
-  std::vector<double> x((size_t)(batch * P.sK) * (wb / 8), 0.0);
-  for (int64_t b = 0; b < batch; ++b)
-    for (int64_t k = 0; k < P.shape.K; ++k) {
-      lam[(size_t)(b * P.sK + k)] = (int32_t)((k * 40503 + 17) & (N - 1));
-      x[(size_t)(b * P.sK + k) * (wb / 8)] = 1.0;
-    }
-  HIP_TRY(hipMemcpyAsync(P.lam, lam.data(), lam.size() * 4, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(P.x, x.data(), x.size() * 8, hipMemcpyHostToDevice, st));
-  HIP_TRY(launch_fill_u32((uint32_t*)P.y_ent, 0u, (int64_t)(batch * P.sM * wb / 4), st));
-  HIP_TRY(launch_fill_u32(P.excl, 0u, batch * P.sE, st));
-  HIP_TRY(launch_fill_u32((uint32_t*)P.h0, 0u, (int64_t)(batch * P.sN * wb / 4), st));
-  HIP_TRY(launch_init_status(P.status, P.y_ent, (int)M, F, P.sM, batch, st));
-  hipEvent_t e0, e1, e2;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  HIP_TRY(hipEventCreate(&e2));
-  int npart = 0;
-  std::vector<int32_t> hord, hbst;
-  // warm up both paths
-  if ((rc = plan_set_tap_order(P, lam.data(), 1, st, hord, hbst)) ||
-      (rc = plan_fast_corr(P, 2, &npart, st)) || (rc = plan_conv_corr(P, 2, &npart, st))) {
-    (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); (void)hipEventDestroy(e2);
-    return rc;
-  }
+  CurveBench C;
+  int rc = curve_setup(C, matrix_class, N, M, corr_precision, batch, tmax, ws_dev, ws_bytes,
+                       (hipStream_t)hip_stream);
+  if (rc) return rc;
   int best = 1;
-  for (int t = 2; t <= P.shape.K; t += std::max(1, (t - 1) / 4)) {
-    if ((rc = plan_set_tap_order(P, lam.data(), t - 1, st, hord, hbst))) break;
-    (void)hipEventRecord(e0, st);
-    for (int r = 0; r < kReps && !rc; ++r) rc = plan_fast_corr(P, t, &npart, st);
-    (void)hipEventRecord(e1, st);
-    for (int r = 0; r < kReps && !rc; ++r) rc = plan_conv_corr(P, t, &npart, st);
-    (void)hipEventRecord(e2, st);
-    if (rc) break;
-    if (hipEventSynchronize(e2) != hipSuccess) { rc = set_error(FCMP_E_DEVICE, "event sync"); break; }
+  for (int t = 2; t <= C.P.shape.K; t += std::max(1, (t - 1) / 4)) {
     float fast_ms = 0.f, conv_ms = 0.f;
-    (void)hipEventElapsedTime(&fast_ms, e0, e1);
-    (void)hipEventElapsedTime(&conv_ms, e1, e2);
+    if ((rc = curve_point(C, t, &fast_ms, &conv_ms))) return rc;
     if (fast_ms <= conv_ms) best = t;
     else break;   // the fast cost only grows with t
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
-  if (rc) return rc;
   set_tuned_switch(matrix_class, N, corr_precision, best);
   *switch_t = best;
   if (cache_path) {
@@ -153,6 +187,41 @@ int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_preci
       return set_error(FCMP_E_INVALID, "cannot append to the cache file");
     }
   }
+  return FCMP_OK;
+}
+
+int fcmp_corr_curve_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
+                                    int32_t corr_precision, int32_t batch, int32_t tmax,
+                                    size_t* bytes) {
+  if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
+  if (tmax < 2) return set_error(FCMP_E_INVALID, "tmax must be >= 2");
+  std::vector<int32_t> om;
+  std::vector<fcmp_problem> probs;
+  fcmp_options opt;
+  int rc = tune_shape(matrix_class, N, M, batch, tmax, om, probs, opt, corr_precision);
+  if (rc) return rc;
+  fcmp_plan P;
+  if ((rc = plan_init(P, batch, probs.data(), &opt))) return rc;
+  *bytes = P.total;
+  return FCMP_OK;
+}
+
+int fcmp_corr_curve(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
+                    int32_t batch, const int32_t* ts, int32_t nt, void* ws_dev, size_t ws_bytes,
+                    float* fast_ms, float* conv_ms, void* hip_stream) {
+  if (!ts || !fast_ms || !conv_ms || nt < 1) return set_error(FCMP_E_INVALID, "bad arrays");
+  int tmax = 2;
+  for (int i = 0; i < nt; ++i) {
+    if (ts[i] < 2) return set_error(FCMP_E_INVALID, "every t must be >= 2");
+    tmax = std::max(tmax, ts[i]);
+  }
+  if (tmax > M - 1) return set_error(FCMP_E_INVALID, "t must be <= M - 1");
+  CurveBench C;
+  int rc = curve_setup(C, matrix_class, N, M, corr_precision, batch, tmax, ws_dev, ws_bytes,
+                       (hipStream_t)hip_stream);
+  if (rc) return rc;
+  for (int i = 0; i < nt; ++i)
+    if ((rc = curve_point(C, ts[i], &fast_ms[i], &conv_ms[i]))) return rc;
   return FCMP_OK;
 }
 

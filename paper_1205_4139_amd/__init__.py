@@ -276,7 +276,7 @@ def _sel_tensor(device):
 
 
 def decode_sel(sel) -> tuple:
-    """(index, |h|^2) from the 16-byte selection record."""
+    """(index, |h|^2) from the selection record {key, index, runner-up key}."""
     a = sel.detach().cpu().numpy()
     key = float(a[0])
     idx = int(a[1:2].view(np.int64)[0])

@@ -96,32 +96,51 @@ def time_steps(fn, steps: int, warmup: int):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(inst, iters: int):
+def cpu_baseline(inst, iters: int, single_iters: int):
     """The FP64 oracle (transform tier) on the first `iters` OMP iterations of
-    one instance of the same workload."""
-    import numpy as np
-
+    one instance of the same workload, with the host's cores (BLAS and FFT
+    threads as they come), then on the first `single_iters` iterations with
+    one thread.  Returns the record and the all-core oracle result (kept h per
+    iteration, for the accuracy block)."""
     import oracle
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_limits
     except Exception:
-        threads = 1
+        threadpool_limits = None
+    cores = len(os.sched_getaffinity(0))
     y = oracle.problem.instance_measure(inst, tier="transform")
     op = oracle.make_operator("F", N, inst.omega, "transform")
     t0 = time.perf_counter()
-    oracle.omp(op, y, iters)
+    ref = oracle.omp(op, y, iters, keep_h=True)
     dt = time.perf_counter() - t0
     byts = S_C128 * M + 4 * M + S_C128 * N
-    return {
+    single = None
+    if threadpool_limits is not None and single_iters > 0:
+        # the same short prefix with all threads and with one, so the two
+        # figures compare like with like (least squares grows with t)
+        t1 = time.perf_counter()
+        oracle.omp(op, y, single_iters)
+        da = time.perf_counter() - t1
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            oracle.omp(op, y, single_iters)
+            d1 = time.perf_counter() - t1
+        single = {"value": round(single_iters * byts / d1 / 1e9, 4), "cores": 1,
+                  "all_cores_same_sample": round(single_iters * byts / da / 1e9, 4),
+                  "sample": f"first {single_iters} OMP iterations: one thread {d1:.2f} s, "
+                            f"all cores {da:.2f} s"}
+    rec = {
         "value": round(iters * byts / dt / 1e9, 4),
         "unit": "GB/s",
-        "cores": int(threads),
+        "cores": int(cores),
         "kind": "oracle",
         "sample": f"1 instance, first {iters} of {K} OMP iterations (conventional, FP64, "
-                  f"numpy FFT + LAPACK lstsq), {dt:.1f} s",
+                  f"numpy FFT + LAPACK lstsq, {cores} cores available to the process), "
+                  f"{dt:.1f} s",
         "solves_per_s_extrapolated": round(iters / K / dt, 6),
+        "single_core": single,
     }
+    return rec, (y, op, ref)
 
 
 def measure_host(fc, inst, device):
@@ -129,6 +148,8 @@ def measure_host(fc, inst, device):
     import numpy as np
     import torch
     x = torch.from_numpy(inst.x_dense()).to(device)
+    if inst.noise is None or inst.snr_db is None:
+        return fc.measure(inst.cls, inst.N, inst.omega, x)
     g = torch.from_numpy(np.ascontiguousarray(inst.noise)).to(device)
     return fc.measure(inst.cls, inst.N, inst.omega, x, g, inst.snr_db)
 
@@ -152,10 +173,19 @@ def batch_leg(fc, device, count: int, steps: int, plain_n: int):
     bp.solve(ys)
     torch.cuda.synchronize()
     t = time_steps(lambda: bp.solve(ys), steps, 0)
-    sup, _x, st = bp.solve(ys, stats=True)
+    sup, xb, st = bp.solve(ys, stats=True)
     done_ms = np.array([s.ms_total for s in st])
     rec = float(np.mean([set(sup[k].cpu().numpy()) == set(insts[k].support)
                          for k in range(count)]))
+    # against the stored oracle solves of six N = 2^14 instances
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                       "uneven_batch4096_seed4000_n16384.json")))
+    par, xerr = 0, 0.0
+    for e in gold["instances"] if count == 4096 else []:
+        k = e["index"]
+        xr = np.array(e["x"]["re"]) + (1j * np.array(e["x"]["im"]) if "im" in e["x"] else 0.0)
+        par += int(list(sup[k].cpu().numpy()) == e["support"])
+        xerr = max(xerr, float(np.linalg.norm(xb[k].cpu().numpy() - xr) / np.linalg.norm(xr)))
     bp.close()
     lat = []
     idx = np.linspace(0, count - 1, plain_n).astype(int)
@@ -175,6 +205,9 @@ def batch_leg(fc, device, count: int, steps: int, plain_n: int):
                           "max": round(float(done_ms.max()), 3)},
         "plan_create_ms": round(t_create * 1e3, 1),
         "support_recovery_rate": rec,
+        "oracle_parity": {"instances": 6 if count == 4096 else 0, "support_equal": par,
+                          "x_rel_err_max": xerr,
+                          "note": "stored FP64 oracle solves of six N = 2^14 instances"},
         "plain": {"solves_per_s": round(1e3 / float(lat.mean()), 2),
                   "p50_ms": round(float(np.percentile(lat, 50)), 3),
                   "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -225,6 +258,177 @@ def serve_leg(fc, device, count: int, rate_hz: float):
         "pool_peak_GiB": round(info["pool_peak"] / 2**30, 2),
         "support_recovery_rate": rec,
     }
+
+
+def _inf_rel(a, b):
+    import numpy as np
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(b)))
+
+
+def accuracy_cfg1(fc, device, insts, ys, sup, x, oracle_run):
+    """Errors against the FP64 oracle beside the workload's numbers: support
+    parity and x error of instance 0 against its stored oracle solve, and the
+    infinity-relative error of h at sampled iterations t, on the oracle's own
+    residual r_{t-1} (conventional correlation) and taps (fast correlation)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                       "omp_fourier_n65536_m16384_k256_seed2000.json")))
+    xr = np.array(gold["x_re"]) + 1j * np.array(gold["x_im"])
+    out = {"instance0_support_equal": list(sup[0]) == gold["support"],
+           "instance0_x_rel_err": float(np.linalg.norm(x[0] - xr) / np.linalg.norm(xr)),
+           "note": "h errors: ||h_gpu - h_oracle||_inf / ||h_oracle||_inf; the conventional "
+                   "path sees the oracle's FP64 residual rounded to complex64"}
+    if oracle_run is None:
+        return out
+    y, op, ref = oracle_run
+    inst = insts[0]
+    c64, cp = fc.kernel_vector("F", N, inst.omega, "fp32", device=device)
+    h0 = torch.from_numpy(np.ascontiguousarray(ref.h[0])).to(device)
+    conv, fast = {}, {}
+    for t in (2, 16, 128, K):
+        lam = ref.support[:t - 1]
+        xt = ref.xs[t - 2]
+        r = y - op.columns(lam) @ xt
+        want = ref.h[t - 1]
+        rd = torch.from_numpy(r.astype(np.complex64)).to(device)
+        h, _ = fc.correlate("F", N, inst.omega, rd, "fp32")
+        conv[str(t)] = _inf_rel(h.cpu().numpy(), want)
+        hf, _ = fc.fast_correlate("F", N, h0, cp, torch.from_numpy(lam.astype(np.int32)).to(device),
+                                  torch.from_numpy(np.ascontiguousarray(xt)).to(device), "fp32")
+        fast[str(t)] = _inf_rel(hf.cpu().numpy(), want)
+    out["h_inf_rel_err_conventional"] = conv
+    out["h_inf_rel_err_fast"] = fast
+    out["tolerance"] = 1e-5
+    return out
+
+
+def cfg0_leg(fc, device, count: int, reps: int):
+    """Partial Hadamard N = 1024, M = 256, K = 16, N(0,1) values, noiseless,
+    FP64, conventional FWHT correlation, plain OMP on one instance per call:
+    host-synchronised latency over `count` instances (seeds 1000+i), beside the
+    dense-tier oracle (Phi formed entry by entry) on the same instances; support
+    parity and x error against that oracle."""
+    import numpy as np
+
+    import instancegen
+    import oracle
+    from oracle import certify
+    insts = [instancegen.draw_config("hadamard_n1024", i) for i in range(count)]
+    ys = [oracle.problem.instance_measure(i) for i in insts]
+    yd = [fc._torch().from_numpy(y).to(device) for y in ys]
+    for i, y in zip(insts[:2], yd[:2]):   # warm-up
+        fc.solve("H", i.N, i.M, i.K, i.omega, y, precision="fp64")
+    lat, sups, xs = [], [], []
+    for _ in range(reps):
+        for i, y in zip(insts, yd):
+            t0 = time.perf_counter()
+            r = fc.solve("H", i.N, i.M, i.K, i.omega, y, precision="fp64", stats=True)
+            lat.append(time.perf_counter() - t0)
+    for i, y in zip(insts, yd):
+        r = fc.solve("H", i.N, i.M, i.K, i.omega, y, precision="fp64")
+        sups.append(r.support.cpu().numpy())
+        xs.append(r.x.cpu().numpy())
+    lat = np.array(lat) * 1e3
+    t0 = time.perf_counter()
+    refs = [oracle.omp(oracle.make_operator("H", i.N, i.omega, "dense"), y, i.K)
+            for i, y in zip(insts, ys)]
+    t_orc = (time.perf_counter() - t0) / count
+    cert = [certify.certified(r, "fp64") for r in refs]
+    same = [list(s) == list(r.support) for s, r in zip(sups, refs)]
+    xerr = [float(np.linalg.norm(xv - r.x) / np.linalg.norm(r.x)) for xv, r in zip(xs, refs)]
+    return {
+        "workload": f"partial Hadamard N=1024 M=256 K=16, N(0,1) values, noiseless, FP64, "
+                    f"conventional, single instance per call ({count} instances x {reps})",
+        "p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "solves_per_s": round(1e3 / float(lat.mean()), 1),
+        "oracle_dense_ms_per_solve": round(t_orc * 1e3, 3),
+        "accuracy": {"certified_fp64": int(sum(cert)), "support_parity_certified":
+                     int(sum(s for s, c in zip(same, cert) if c)),
+                     "support_parity_all": int(sum(same)), "x_rel_err_max": max(xerr)},
+    }
+
+
+def cfg2_leg(fc, device):
+    """Partial Hadamard N = 2^20, M = 2^17, K = 1024, +-U(1,2) values,
+    noiseless (instance 0, seed 3000), FP32 correlation and FP64 least
+    squares: OMP (conventional, adaptive), SP and CoSaMP (conventional, fast),
+    one solve each per call, against the stored FP64 oracle solves; the
+    conventional correlation's throughput from the solve's own phase times."""
+    import numpy as np
+
+    import instancegen
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden",
+                                       "hadamard_n1m_m131072_k1024_seed3000.json")))
+    inst = instancegen.draw_config("hadamard_n1m", 0)
+    y = measure_host(fc, inst, device)
+    NN, MM, KK = inst.N, inst.M, inst.K
+    out = {"workload": "partial Hadamard N=2^20 M=2^17 K=1024, +-U(1,2) values, noiseless, "
+                       "FP32 correlation + FP64 LS, single instance"}
+    fc.solve("H", NN, MM, KK, inst.omega, y, precision="fp32")   # warm-up
+    for alg, methods in (("omp", ("conventional", "adaptive")), ("sp", ("conventional", "fast")),
+                         ("cosamp", ("conventional", "fast"))):
+        ref = gold[alg]
+        xr = np.array(ref["x"]["re"])
+        for meth in methods:
+            t0 = time.perf_counter()
+            r = fc.solve("H", NN, MM, KK, inst.omega, y, algorithm=alg, method=meth,
+                         precision="fp32", flags=fc.FLAG_PHASE_TIMES)
+            wall = time.perf_counter() - t0
+            s = r.stats
+            sup = r.support.cpu().numpy()
+            xv = r.x.cpu().numpy()
+            o1, o2 = np.argsort(sup), np.argsort(ref["support"])
+            rec = {"ms_per_solve": round(wall * 1e3, 2), "device_ms": round(s.ms_total, 2),
+                   "ms_corr": round(s.ms_corr, 2), "ms_ls": round(s.ms_ls, 2),
+                   "ms_select": round(s.ms_select, 2), "iterations": int(s.iterations),
+                   "support_set_equal": sorted(sup.tolist()) == sorted(ref["support"]),
+                   "x_rel_err": float(np.linalg.norm(xv[o1] - xr[o2]) / np.linalg.norm(xr))}
+            if alg == "omp":
+                g = np.array(gold["omp"]["gaps"])
+                first = int(np.argmax(g < 2.5e-5))
+                rec["order_equal_to_first_uncertified_gap"] = (
+                    list(sup[:first]) == gold["omp"]["support"][:first])
+                rec["first_uncertified_iteration"] = first
+                rec["min_gap"] = float(s.min_gap)
+                if meth == "conventional":
+                    per = s.ms_corr / KK
+                    byts = 4 * MM + 4 * MM + 4 * NN
+                    rec["corr_us_per_iteration"] = round(per * 1e3, 2)
+                    rec["corr_GBps_algorithmic"] = round(byts / (per / 1e3) / 1e9, 1)
+            out[f"{alg}_{meth}"] = rec
+    return out
+
+
+def per_t_leg(fc, device):
+    """Per-iteration device time of the fast (eq. (kernelsumOMP)) and the
+    conventional correlation as a function of the iteration t, at batch 1 and
+    at the benchmark's batch for the partial-Fourier workload, and at batch 1
+    for the N = 2^20 Hadamard workload; with the fast method's compulsory HBM
+    bytes (h_0 FP64, kernel vector, h, taps) and the kernel-vector gather bytes
+    per instance: s64 N + 2 N s + (4 + s64)(t - 1) and (t - 1) N s."""
+    out = {}
+    for name, cls, NN, MM, prec, s, s64, batches, ts in (
+            ("fourier_n65536_c64", "F", N, M, "fp32", 8, 16, (1, 256),
+             (2, 4, 8, 16, 32, 64, 128, 256)),
+            ("hadamard_n1m_fp32", "H", 1 << 20, 1 << 17, "fp32", 4, 8, (1,),
+             (2, 8, 21, 64, 256, 1024))):
+        for b in batches:
+            fast, conv = fc.corr_curve(cls, NN, MM, ts, precision=prec, batch=b, device=device)
+            rows = []
+            for t, f, c in zip(ts, fast, conv):
+                comp = b * (s64 * NN + 2 * NN * s + (4 + s64) * (t - 1))
+                gath = b * (t - 1) * NN * s
+                rows.append({"t": t, "fast_ms": round(f, 4), "conv_ms": round(c, 4),
+                             "fast_hbm_frac": round(comp / (f / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "fast_gather_GBps": round(gath / (f / 1e3) / 1e9, 1)})
+            cross = [r["t"] for r in rows if r["fast_ms"] <= r["conv_ms"]]
+            out[f"{name}_batch{b}"] = {"points": rows,
+                                       "fast_cheaper_up_to_t": max(cross) if cross else 1}
+    return out
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
@@ -297,6 +501,12 @@ def main():
     ap.add_argument("--fast-steps", type=int, default=1)
     ap.add_argument("--plain", type=int, default=6, help="single-instance solves to time")
     ap.add_argument("--cpu-iters", type=int, default=256)
+    ap.add_argument("--cpu-single-iters", type=int, default=64,
+                    help="OMP iterations of the one-thread CPU baseline")
+    ap.add_argument("--cfg0-count", type=int, default=64,
+                    help="N = 1024 Hadamard single-instance leg: instances (0: skip)")
+    ap.add_argument("--no-cfg2", action="store_true", help="skip the N = 2^20 Hadamard leg")
+    ap.add_argument("--no-per-t", action="store_true", help="skip the per-iteration cost curves")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
@@ -360,6 +570,7 @@ def main():
     sup, x, _ = plan.solve(ys, method="conventional", stats=False)
     torch.cuda.synchronize()
     sup_np = sup.cpu().numpy().copy()
+    x_np = x.cpu().numpy().copy()
     recovered = float(np.mean([set(sup[i].cpu().numpy()) == set(insts[i].support)
                                for i in range(B)]))
 
@@ -444,6 +655,22 @@ def main():
         serve_low = serve_leg(fc, dev, args.serve_sustained, args.serve_sustained_rate)
         print(f"[bench] serve (sustained rate): {serve_low}", file=sys.stderr, flush=True)
 
+    cfg0 = cfg2 = per_t = None
+    if args.cfg0_count > 0:
+        cfg0 = cfg0_leg(fc, dev, args.cfg0_count, 3)
+        print(f"[bench] cfg0: {cfg0}", file=sys.stderr, flush=True)
+    if not args.no_cfg2:
+        cfg2 = cfg2_leg(fc, dev)
+        print(f"[bench] cfg2: {cfg2}", file=sys.stderr, flush=True)
+    if not args.no_per_t:
+        per_t = per_t_leg(fc, dev)
+        print(f"[bench] per-t: {per_t}", file=sys.stderr, flush=True)
+    cpu_rec = orc = None
+    if not args.no_cpu:
+        cpu_rec, orc = cpu_baseline(insts[0], args.cpu_iters, args.cpu_single_iters)
+    accuracy = accuracy_cfg1(fc, dev, insts, ys, sup_np, x_np, orc)
+    print(f"[bench] accuracy: {accuracy}", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -471,6 +698,9 @@ def main():
         "uneven_batch": batch,
         "serving": serve,
         "serving_sustained": serve_low,
+        "accuracy": accuracy,
+        "configs": {"hadamard_n1024_single": cfg0, "hadamard_n1m": cfg2},
+        "per_t": per_t,
         "roofline": {
             "kernel": "conventional correlation launch pair, B instances: the FP64 residual "
                       "fused with the complex64 first pass (rcorr_kernel), then the second "
@@ -486,8 +716,8 @@ def main():
             "avg_launch_ms": round(corr_ms / max(corr_n, 1), 5),
         },
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(insts[0], args.cpu_iters)
+    if cpu_rec is not None:
+        out["cpu_baseline"] = cpu_rec
     print(json.dumps(out))
 
 

@@ -554,6 +554,15 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
   if (P.opt.algorithm != FCMP_OMP) {
     rc = plan_enqueue_prefix(P, opt, st);
     if (!rc) rc = plan_solve_set(P, opt, (int32_t* const*)sup, xo, stats, st);
+    if (e1 && (!rc || rc == FCMP_E_NUMERIC)) {
+      // the loops synchronise the stream themselves; the solve's device time
+      float ms = 0.f;
+      hipError_t e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e == hipSuccess)
+        for (int64_t b = 0; b < P.n; ++b) stats[b].ms_total = ms;
+    }
     drop_events();
     if (phase_times && (!rc || rc == FCMP_E_NUMERIC)) {
       const int prc = solve_times_read(stm, pms);

@@ -246,3 +246,14 @@ def test_correlate_identification_only(fc, cls, N, precision):
             assert idx not in top[:skip]
             assert np.sqrt(a[idx]) >= np.sqrt(a[best]) - 2 * TOL[precision] * np.sqrt(a[top[0]])
         assert abs(np.sqrt(key) - np.sqrt(a[idx])) <= TOL[precision] * np.sqrt(a[top[0]])
+
+
+def test_corr_curve(fc):
+    """fcmp_corr_curve: positive device times at every iteration; the fast
+    correlation's cost grows with the tap count while the conventional one's
+    does not (its residual taps are summed per column, a small share)."""
+    ts = [2, 16, 128]
+    fast, conv = fc.corr_curve("F", 16384, 4096, ts, precision="fp32", batch=4)
+    assert all(f > 0 for f in fast) and all(c > 0 for c in conv)
+    assert fast[2] > fast[0]
+    assert conv[2] < 4 * conv[0]

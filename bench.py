@@ -461,9 +461,9 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
         grids = Counter()
         for r in rows:
             name = r["Kernel_Name"]
-            if "rcorr_kernel<true, HIP_vector_type<float, 2u>" in name:
+            if "rcorr_reg_kernel<true, HIP_vector_type<float, 2u>" in name:
                 key = "pass1"
-            elif "xform_kernel<HIP_vector_type<float, 2u>, true, 2>" in name:
+            elif "xrow_kernel<HIP_vector_type<float, 2u>, true, 1>" in name:
                 key = "pass2"
             else:
                 continue
@@ -490,6 +490,40 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
     return out
 
 
+def summarize_sq(csv_path: str) -> dict:
+    """Per-kernel SQ counter ratios from one rocprofv3 --pmc run of this script
+    (the workload's grid, i.e. the most frequent grid of each kernel): each
+    counter divided by SQ_WAVE_CYCLES, the medians over that grid's dispatches."""
+    import csv
+    import statistics
+    from collections import Counter, defaultdict
+    rows = list(csv.DictReader(open(csv_path)))
+    vals = defaultdict(lambda: defaultdict(dict))
+    grids = Counter()
+    for r in rows:
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+        key = (name, int(r["Grid_Size"]))
+        vals[key][r["Dispatch_Id"]][r["Counter_Name"]] = float(r["Counter_Value"])
+        if r["Counter_Name"] == "SQ_WAVE_CYCLES":
+            grids[key] += 1
+    out = {}
+    for name in {k[0] for k in grids}:
+        g = max((k for k in grids if k[0] == name), key=lambda k: grids[k])
+        if grids[g] < 10:
+            continue
+        ratios = defaultdict(list)
+        for d in vals[g].values():
+            wc = d.get("SQ_WAVE_CYCLES", 0.0)
+            if wc <= 0:
+                continue
+            for c, v in d.items():
+                if c != "SQ_WAVE_CYCLES":
+                    ratios[c].append(v / wc)
+        out[name] = {"grid": g[1], "dispatches": grids[g],
+                     **{c: round(statistics.median(v), 4) for c, v in sorted(ratios.items())}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -507,6 +541,8 @@ def main():
                     help="N = 1024 Hadamard single-instance leg: instances (0: skip)")
     ap.add_argument("--no-cfg2", action="store_true", help="skip the N = 2^20 Hadamard leg")
     ap.add_argument("--no-per-t", action="store_true", help="skip the per-iteration cost curves")
+    ap.add_argument("--only", choices=("cfg0", "cfg2", "batch", "per_t"),
+                    help="run that leg alone and print its record (for profiling); no metric line")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
@@ -519,9 +555,14 @@ def main():
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_traffic.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--summarize-sq", metavar="CSV",
+                    help="print per-kernel SQ counter ratios of one rocprofv3 --pmc run and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(*args.summarize_pmc)))
+        return
+    if args.summarize_sq:
+        print(json.dumps(summarize_sq(args.summarize_sq), indent=1))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -543,6 +584,17 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only:
+        if args.only == "cfg0":
+            rec = cfg0_leg(fc, dev, max(args.cfg0_count, 1), 3)
+        elif args.only == "cfg2":
+            rec = cfg2_leg(fc, dev)
+        elif args.only == "batch":
+            rec = batch_leg(fc, dev, args.batch_count, max(args.steps, 1), 8)
+        else:
+            rec = per_t_leg(fc, dev)
+        print(json.dumps({"leg": args.only, "record": rec}))
+        return
     B = args.batch
     insts, ys = make_inputs(B, dev)
     print(f"[bench] inputs ready: B={B} N={N} M={M} K={K}", file=sys.stderr, flush=True)
@@ -703,8 +755,8 @@ def main():
         "per_t": per_t,
         "roofline": {
             "kernel": "conventional correlation launch pair, B instances: the FP64 residual "
-                      "fused with the complex64 first pass (rcorr_kernel), then the second "
-                      "pass with the identification (xform_kernel role 2); the residual's "
+                      "fused with the complex64 first pass (rcorr_reg_kernel), then the "
+                      "second pass with the identification (xrow_kernel); the residual's "
                       "time is charged to the correlation",
             "bound": "hbm",
             "achieved": round(achieved, 2),

@@ -20,7 +20,9 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfcmp.so")
+# FCMP_LIBRARY selects another build of the same library (the host-sanitizer
+# builds of paper_1205_4139_amd/build.py); there is no fallback when it is absent.
+LIB_PATH = os.environ.get("FCMP_LIBRARY") or os.path.join(_HERE, "libfcmp.so")
 
 HADAMARD, FOURIER = 0, 1
 OMP, SP, COSAMP = 0, 1, 2

@@ -1,6 +1,6 @@
 // LDS-resident transforms shared by the transform kernels and the
 // persistent per-instance OMP kernel: two-level twiddle lookup, value
-// conversions and the in-place radix-8 FFT / WHT over B interleaved sequences.
+// conversions and the in-place radix-16 FFT / WHT over B interleaved sequences.
 #pragma once
 #include "kernels.h"
 

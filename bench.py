@@ -244,12 +244,18 @@ def serve_leg(fc, device, count: int, rate_hz: float):
     done = np.array([r["times"][2] for r in res])
     lat = done - sub
     span = (done.max() - sub.min()) / 1e3
+    # completion rate over the arrival window: requests finished by the last
+    # arrival per second of the window (at a sustainable rate this tracks the
+    # offered rate, short of the first latency period)
+    window = max((sub.max() - sub.min()) / 1e3, 1e-9)
+    in_window = float(np.sum(done <= sub.max()) / window)
     rec = float(np.mean([set(r["support"]) == set(i.support) for r, i in zip(res, insts)]))
     return {
         "workload": f"{count}-request Poisson stream at {rate_hz:.0f} req/s: F/H, N = 2^U{{12..18}}, "
                     "M ~ U{N/8..N/4}, K ~ U{16..M/16}, 30 dB, complex64/FP32 correlation",
         "offered_req_per_s": round(count / max(t_sub, 1e-9), 1),
         "completed_req_per_s": round(float(count / span), 1),
+        "completed_in_window_per_s": round(in_window, 1),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 2),
                        "p99": round(float(np.percentile(lat, 99)), 2)},
         "queue_ms": {"p50": round(float(np.percentile(launch - sub, 50)), 2),
@@ -431,6 +437,28 @@ def per_t_leg(fc, device):
     return out
 
 
+def serve_sweep(fc, device, rates, seconds: float):
+    """The serving stream at increasing offered rates (each `seconds` of
+    arrivals); stops after the first rate whose completion rate over the
+    arrival window falls below 95% of the offered rate.  The sustained rate is
+    the highest offered rate that kept up."""
+    runs, sustained = [], None
+    for rate in rates:
+        count = max(100, int(rate * seconds))
+        r = serve_leg(fc, device, count, rate)
+        r["kept_up"] = r["completed_in_window_per_s"] >= 0.95 * r["offered_req_per_s"]
+        runs.append(r)
+        print(f"[bench] serve sweep {rate}: {r}", file=sys.stderr, flush=True)
+        if not r["kept_up"]:
+            break
+        sustained = r
+    return {"runs": runs,
+            "sustained_req_per_s": sustained["offered_req_per_s"] if sustained else None,
+            "at_sustained": ({k: sustained[k] for k in ("completed_in_window_per_s", "latency_ms",
+                                                         "queue_ms")} if sustained else None),
+            "criterion": "completed within the arrival window >= 95% of offered"}
+
+
 def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
     """HBM bytes per conventional-correlation launch pair (the residual fused
     with the complex64 first pass, then pass 2, at the workload's grid) from two rocprofv3 --pmc runs of this
@@ -547,9 +575,11 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
-    ap.add_argument("--serve-sustained", type=int, default=200,
-                    help="requests of a second stream at --serve-sustained-rate (0: skip)")
-    ap.add_argument("--serve-sustained-rate", type=float, default=100.0)
+    ap.add_argument("--serve-sweep", type=str, default="100,200,400,800,1600",
+                    help="offered rates (req/s) of the serving sweep, '' to skip")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="seconds of arrivals per sweep rate")
+    ap.add_argument("--serve-sustained", type=int, default=1, help="0: skip the serving sweep")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (the reference "
                          "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -703,9 +733,9 @@ def main():
         serve = serve_leg(fc, dev, args.serve_requests, args.serve_rate)
         print(f"[bench] serve: {serve}", file=sys.stderr, flush=True)
     serve_low = None
-    if args.serve_sustained > 0:
-        serve_low = serve_leg(fc, dev, args.serve_sustained, args.serve_sustained_rate)
-        print(f"[bench] serve (sustained rate): {serve_low}", file=sys.stderr, flush=True)
+    if args.serve_sweep and args.serve_sustained:
+        serve_low = serve_sweep(fc, dev, [float(r) for r in args.serve_sweep.split(",") if r],
+                                args.serve_seconds)
 
     cfg0 = cfg2 = per_t = None
     if args.cfg0_count > 0:
@@ -749,7 +779,7 @@ def main():
         "phases": phases,
         "uneven_batch": batch,
         "serving": serve,
-        "serving_sustained": serve_low,
+        "serving_sweep": serve_low,
         "accuracy": accuracy,
         "configs": {"hadamard_n1024_single": cfg0, "hadamard_n1m": cfg2},
         "per_t": per_t,

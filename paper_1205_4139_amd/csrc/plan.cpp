@@ -2,9 +2,11 @@
 // correlation method), n instances of one shape per launch.
 #include "plan.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 
 namespace fcmp {
 
@@ -217,24 +219,41 @@ int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st) {
     goff2.assign((size_t)(n * P.sG2), 0);
     pos1.assign((size_t)(n * P.sM), 0);
   }
-  HostTables t;
-  for (int64_t b = 0; b < n; ++b) {
-    const int64_t M = probs[b].M;
-    build_tables(P.g, probs[b].omega, (int)M, t);
-    std::memcpy(&ent[b * P.sM], t.ent_k.data(), M * 4);
-    std::memcpy(&perm[b * P.sM], t.perm.data(), M * 4);
-    std::memcpy(&goff[b * P.sG], t.goff.data(), t.goff.size() * 4);
-    if (P.rreg) {
-      std::memcpy(&cmask[b * P.sC], t.cmask.data(), t.cmask.size() * 4);
-      std::memcpy(&cbase[b * P.sC], t.cbase.data(), t.cbase.size() * 4);
+  // the per-instance tables are independent: built by up to eight host
+  // threads for large plans, each with its own table set
+  int64_t work = 0;
+  for (int64_t b = 0; b < n; ++b) work += probs[b].M + P.g.N / 8;
+  const int64_t hw = (int64_t)std::max(1u, std::thread::hardware_concurrency());
+  const int nth = (int)std::max<int64_t>(1, std::min<int64_t>({n, 8, hw, work / (1 << 18) + 1}));
+  std::vector<HostTables> tset((size_t)nth);
+  auto fill = [&](int th) {
+    HostTables& t = tset[(size_t)th];
+    for (int64_t b = th; b < n; b += nth) {
+      const int64_t M = probs[b].M;
+      build_tables(P.g, probs[b].omega, (int)M, t);
+      std::memcpy(&ent[b * P.sM], t.ent_k.data(), M * 4);
+      std::memcpy(&perm[b * P.sM], t.perm.data(), M * 4);
+      std::memcpy(&goff[b * P.sG], t.goff.data(), t.goff.size() * 4);
+      if (P.rreg) {
+        std::memcpy(&cmask[b * P.sC], t.cmask.data(), t.cmask.size() * 4);
+        std::memcpy(&cbase[b * P.sC], t.cbase.data(), t.cbase.size() * 4);
+      }
+      if (P.cst) std::memcpy(&cst[b * P.sCs], t.cst.data(), t.cst.size() * 4);
+      if (!P.g.same_out) {
+        std::memcpy(&ent2[b * P.sM], t.ent2_k.data(), M * 4);
+        std::memcpy(&goff2[b * P.sG2], t.goff2.data(), t.goff2.size() * 4);
+        std::memcpy(&pos1[b * P.sM], t.pos1.data(), M * 4);
+      }
     }
-    if (P.cst) std::memcpy(&cst[b * P.sCs], t.cst.data(), t.cst.size() * 4);
-    if (!P.g.same_out) {
-      std::memcpy(&ent2[b * P.sM], t.ent2_k.data(), M * 4);
-      std::memcpy(&goff2[b * P.sG2], t.goff2.data(), t.goff2.size() * 4);
-      std::memcpy(&pos1[b * P.sM], t.pos1.data(), M * 4);
-    }
+  };
+  if (nth == 1) {
+    fill(0);
+  } else {
+    std::vector<std::thread> ths;
+    for (int th = 0; th < nth; ++th) ths.emplace_back(fill, th);
+    for (std::thread& th : ths) th.join();
   }
+  const HostTables& t = tset[0];
   if (!P.g.same_out) {
     HIP_TRY(hipMemcpyAsync(P.ent2_k, ent2.data(), ent2.size() * 4, hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(P.goff2, goff2.data(), goff2.size() * 4, hipMemcpyHostToDevice, st));

@@ -6,8 +6,8 @@
 //  * a persistent wave: every queued OMP problem the one-workgroup-per-problem
 //    kernel takes (up to max_wave, same options), solved in one launch;
 //  * a lockstep wave: requests the persistent kernel does not take (large N
-//    or K, SP, CoSaMP) that share class and N (and, for OMP, K within a
-//    factor of two; for SP and CoSaMP, M and K), solved as one lockstep plan.
+//    or K, SP, CoSaMP) that share class and N (for SP and CoSaMP also M and
+//    K), solved as one lockstep plan.
 // With several streams worker 0 runs persistent waves only, so small requests
 // never queue behind large ones; the other workers take the oldest large
 // request first.  Waves on different streams overlap on the device.  Each request's device state
@@ -115,18 +115,13 @@ bool same_opts(const fcmp_options& a, const fcmp_options& b) {
          a.switch_t == b.switch_t && a.flags == b.flags;
 }
 
-int log2_ceil(int64_t v) {
-  int l = 0;
-  while ((int64_t(1) << l) < v) ++l;
-  return l;
-}
-
 // Requests that may share a lockstep wave: OMP plans take per-instance M and
-// K, so (class, N) and K within a factor of two (a wave ends with its
-// longest solve); SP and CoSaMP need one shape.
+// K, so one (class, N) (an instance whose K selections are made stops taking
+// device time; the wave ends with its longest solve); SP and CoSaMP need one
+// shape.
 bool same_group(const fcmp_problem& a, const fcmp_problem& b, int algorithm) {
   if (a.matrix_class != b.matrix_class || a.N != b.N) return false;
-  if (algorithm == FCMP_OMP) return log2_ceil(a.K) == log2_ceil(b.K);
+  if (algorithm == FCMP_OMP) return true;
   return a.M == b.M && a.K == b.K;
 }
 

@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define FCMP_ABI_VERSION 2
+#define FCMP_ABI_VERSION 3
 
 /* status codes */
 #define FCMP_OK            0
@@ -265,26 +265,36 @@ int fcmp_plan_destroy(fcmp_plan* plan);
 /* ---- serving ---------------------------------------------------------- */
 
 /* A solver service with continuous batching.  Requests (problem, options,
- * y on the HOST) queue on submit; worker threads, one per HIP stream the
- * server creates (default priority), admit them in arrival order whenever
- * request slots and room in the caller's device pool allow, and run them as
- * waves: all queued OMP requests the persistent one-workgroup-per-problem
- * kernel takes, with the same options, in one persistent launch (at most
- * max_wave); any other request as a lockstep plan with the queued requests
- * of its class and N (OMP: K within a factor of two; SP/CoSaMP: same M, K).  With several streams, stream 0 runs persistent waves only.
- * Waves on different
- * streams overlap on the device.  A request's device state stays in its
- * wave's pool region from admission to completion; results are copied to
- * host memory and the region is returned to the pool.  A request's results
- * do not depend on which other requests it shared a wave with.
- * The library never allocates device memory beyond the pool (pinned host
- * staging is allocated per worker). */
+ * y on the HOST) queue on submit and are admitted in arrival order whenever
+ * request slots and room in the caller's device pool allow:
+ *  - slot groups (iteration-granular): OMP requests with the conventional
+ *    correlation whose residual is fused with the transform (two-pass N)
+ *    join a resident group of slots of their class, N and options between
+ *    two iterations, run their own iteration count in lockstep with the
+ *    others, and leave as soon as their K selections are made, so a request
+ *    never waits for a wave to end.  Each group has its own thread and
+ *    stream (at most max_groups); its Omega tables are prepared on host
+ *    threads, kept in a cache keyed by (class, N, Omega), and a slot whose
+ *    device tables already hold the request's Omega (or another slot's
+ *    copy) reuses them with no host work;
+ *  - waves, on worker streams: all queued OMP requests the persistent
+ *    one-workgroup-per-problem kernel takes, with the same options, in one
+ *    persistent launch (at most max_wave); any other request as a lockstep
+ *    plan with the queued requests of its class and N (SP/CoSaMP: same M
+ *    and K).  With several worker streams, stream 0 runs persistent waves.
+ * Work on different streams overlaps on the device.  A request's device
+ * state stays in its slot or wave region from admission to completion;
+ * results are copied to host memory.  A request's results do not depend on
+ * the requests it shares a group or wave with, nor on when it joined.  The
+ * library never allocates device memory beyond the pool (pinned host
+ * staging is allocated per worker and per group). */
 typedef struct fcmp_server fcmp_server;
 typedef struct {
   int32_t max_slots;         /* requests on the device at once (0: 4096) */
   int32_t max_pending;       /* queued, not yet admitted (0: 65536); more: FCMP_E_BUSY */
   int32_t n_streams;         /* worker streams, 1..8 (0: 4) */
   int32_t max_wave;          /* requests per persistent wave (0: 1024) */
+  int32_t max_groups;        /* slot groups at once, 1..16 (0: 8; -1: none, waves only) */
 } fcmp_server_config;
 typedef struct {             /* milliseconds on the server's clock (from creation) */
   double t_submit;           /* fcmp_server_submit returned the ticket */
@@ -294,6 +304,13 @@ typedef struct {             /* milliseconds on the server's clock (from creatio
 typedef struct {
   int64_t submitted, completed, queued, inflight, waves;
   int64_t pool_peak;         /* most pool bytes in use at once */
+  int64_t groups;            /* slot groups created */
+  int64_t slot_joins;        /* requests that joined a slot group */
+  int64_t slot_steps;        /* iterations run by slot groups */
+  int64_t tables_built;      /* Omega tables built on the host */
+  int64_t tables_cached;     /* ... found in the host table cache instead */
+  int64_t tables_resident;   /* joins whose slot already held the tables */
+  int64_t tables_copied;     /* joins that copied another slot's tables */
 } fcmp_server_info;
 
 /* Device pool bytes one request occupies when admitted alone (solver state

@@ -72,7 +72,8 @@ FLAG_PHASE_TIMES = 16
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("max_pending", ctypes.c_int32),
-                ("n_streams", ctypes.c_int32), ("max_wave", ctypes.c_int32)]
+                ("n_streams", ctypes.c_int32), ("max_wave", ctypes.c_int32),
+                ("max_groups", ctypes.c_int32)]
 
 
 class Times(ctypes.Structure):
@@ -83,7 +84,11 @@ class Times(ctypes.Structure):
 class ServerInfo(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("inflight", ctypes.c_int64),
-                ("waves", ctypes.c_int64), ("pool_peak", ctypes.c_int64)]
+                ("waves", ctypes.c_int64), ("pool_peak", ctypes.c_int64),
+                ("groups", ctypes.c_int64), ("slot_joins", ctypes.c_int64),
+                ("slot_steps", ctypes.c_int64), ("tables_built", ctypes.c_int64),
+                ("tables_cached", ctypes.c_int64), ("tables_resident", ctypes.c_int64),
+                ("tables_copied", ctypes.c_int64)]
 
 
 class Profile(ctypes.Structure):
@@ -515,9 +520,9 @@ class Server:
     the request runs, else a dict with support, x, stats and times."""
 
     def __init__(self, pool_bytes, max_slots=0, max_pending=0, n_streams=0, max_wave=0,
-                 device="cuda"):
+                 max_groups=0, device="cuda"):
         self.pool = _workspace(int(pool_bytes), device)
-        cfg = ServerConfig(max_slots, max_pending, n_streams, max_wave)
+        cfg = ServerConfig(max_slots, max_pending, n_streams, max_wave, max_groups)
         self._h = ctypes.c_void_p(0)
         _check(lib.fcmp_server_create(ctypes.byref(self._h), _ptr(self.pool), self.pool.numel(),
                                       ctypes.byref(cfg)))

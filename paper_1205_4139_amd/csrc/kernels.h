@@ -99,8 +99,13 @@ hipError_t launch_taps_pass1(const XParams& a, int vk, int groups, int ninst, hi
 struct RCParams {
   int N, logN, twS;
   int L, logL, B, logN1;   // L = N2 and B columns (k mod N1) per workgroup
+  // taps: ord and bstart hold two buffers per instance (the parity of the tap
+  // count selects one, ord_half / bstart_half apart)
   const int32_t* lam; const void* x; const int32_t* ord; const int32_t* bstart; int ntaps;
-  int64_t inst_lam, inst_x, inst_ord, inst_bstart;
+  int64_t inst_lam, inst_x, inst_ord, inst_bstart, ord_half, bstart_half;
+  // nullable: per-instance iteration offsets (instance i has ntaps - tofs[i]
+  // taps) and K (an instance with K taps made is skipped)
+  const int32_t* tofs; const int32_t* Kv;
   const int32_t* ent_k;    // rows of Omega, sorted by column (k mod N1), then by row
   const int32_t* goff;     // entry index of the first row of each column (N1 + 1 values)
   const void* y;           // FP64 (wide) in entry order
@@ -179,6 +184,7 @@ struct LParams {
   int N;
   int fourier;
   int t;                   // this call makes selection number t (1-based)
+  const int32_t* tofs;     // nullable: instance i makes selection t - tofs[i]
   const Sel* partial;  int npart;
   const void* c64;         // FP64 kernel vector (Gram entries)
   const void* h0;          // FP64 h_0 = Phi^H y (right-hand side b = h0(Lambda))
@@ -201,8 +207,22 @@ struct LParams {
   int nbuck, bshift;
 };
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st);
-int ls_split_groups(int t);   // workgroups per instance used at iteration t
 constexpr int LS_MAX_GROUPS = 256;  // most partial rows of w^H W (long supports)
+// Workgroups per instance of the least-squares update at iteration t (1: the
+// one-workgroup kernel); a function of t only, so every sum's order is too.
+__host__ __device__ inline int ls_split_groups(int t) {
+  const int n = t - 1;
+  if (n < 64) return 1;
+  int G = n / 24;
+  if (G < 2) G = 2;
+  if (G > LS_MAX_GROUPS) G = LS_MAX_GROUPS;
+  return G;
+}
+// Instances at different iterations (tofs set): p.t is the step, instance i
+// makes selection p.t - tofs[i], and t_lo / t_hi bound those of the instances
+// that are not done.
+hipError_t launch_ls_update_slots(const LParams& p, int ninst, int t_lo, int t_hi,
+                                  hipStream_t st);
 
 // ------------------------------------------------------------------ utilities
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
@@ -219,6 +239,8 @@ hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam
 hipError_t launch_reduce_sel(const Sel* partial, int n, Sel* out, hipStream_t st);
 // Mv / Kv (nullable): per-instance counts, at most M / K; NULL: M / K for all.
 // res_tol2: a solve stops once ||r||^2 <= res_tol2 ||y||^2 (0: never)
+// Marks n status records done (every later iteration kernel skips them).
+hipError_t launch_status_done(Status* s, int n, hipStream_t st);
 hipError_t launch_init_status(Status* st_dev, const void* y, int M, int fourier,
                               int64_t inst_y, int ninst, hipStream_t st,
                               const int32_t* Mv = nullptr, double res_tol2 = 0.0);

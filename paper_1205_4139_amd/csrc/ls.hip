@@ -150,14 +150,16 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
   const int inst = blockIdx.x;
   Status* st = p.status + inst;
   if (st->done) return;
-  if (p.Kv && p.t > p.Kv[inst]) {   // its K selections are made
+  const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
+  if (p.tofs && ls_split_groups(t) > 1) return;   // the split update takes it
+  if (p.Kv && t > p.Kv[inst]) {   // its K selections are made
     __syncthreads();
     if (threadIdx.x == 0) st->done = 1;
     return;
   }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nwaves = L_THREADS / 64;
-  const int n = p.t - 1;     // previous selections
+  const int n = t - 1;       // previous selections
   Wd* g = (Wd*)smem_raw;     // g, then the new row of W
   Wd* w = g + (n > 0 ? n : 1);
   int32_t* sl = (int32_t*)(w + (n > 0 ? n : 1));
@@ -263,7 +265,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
     uint32_t* ex = p.excl + (int64_t)inst * p.inst_excl;
     ex[j >> 5] |= 1u << (j & 31);
     st->znorm2 += vmag2(zt);
-    st->iterations = p.t;
+    st->iterations = t;
     st->last_key = best.key;
     st->min_gap = fmin(st->min_gap, sel_gap(best));
     // optional early stop on the residual norm, ||r||^2 = ||y||^2 - ||z||^2
@@ -286,7 +288,9 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   __shared__ Sel red[16];
   const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int n = p.t - 1;
+  const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
+  if (p.tofs && ls_split_groups(t) == 1) return;   // the one-workgroup update takes it
+  const int n = t - 1;
   Status* st = p.status + inst;
   // loads whose addresses do not depend on the outcome go out together: the
   // status, the first partials and the first selected columns
@@ -295,7 +299,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   const Sel s0 = tid < p.npart ? part[tid] : Sel{-1.0, -1, -1.0};
   const int32_t l0 = tid < n ? lam[tid] : 0;
   if (st->done) return;
-  if ((p.Kv && p.t > p.Kv[inst]) ||   // its K selections are made
+  if ((p.Kv && t > p.Kv[inst]) ||   // its K selections are made
       (st->res_tol2 > 0.0 && st->ynorm2 - st->znorm2 <= st->res_tol2 * st->ynorm2)) {
     // (or the residual met the tolerance after the previous update; every
     // workgroup of this launch reads the same record and returns)
@@ -364,11 +368,15 @@ __device__ __forceinline__ bool ls_d(const LParams& p, int inst, int n, double* 
 template <bool FOURIER, int KPT>
 __global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
-  const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
+  const int inst = blockIdx.y, gid = blockIdx.x;
   Status* st = p.status + inst;
   if (st->done) return;
+  const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
+  // the row split is that of the instance's own iteration
+  const int G = p.tofs ? ls_split_groups(t) : (int)gridDim.x;
+  if (G == 1 || gid >= G) return;
   const int tid = threadIdx.x;
-  const int n = p.t - 1;
+  const int n = t - 1;
   // the partial sums do not need d: the breakdown test is left to ls_c
   const Wd* w = (const Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
   const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
@@ -386,14 +394,17 @@ __global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
 }
 
 template <bool FOURIER>
-__global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int G) {
+__global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int Gl) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
   __shared__ double dred[16];
   const int inst = blockIdx.y, cb = blockIdx.x;
   Status* st = p.status + inst;
   if (st->done) return;
+  const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
+  const int G = p.tofs ? ls_split_groups(t) : Gl;
+  if (G == 1) return;
   const int tid = threadIdx.x;
-  const int n = p.t - 1;
+  const int n = t - 1;
   double invd, wzr, wzi;
   if (!ls_d<FOURIER>(p, inst, n, dred, invd, wzr, wzi)) {
     if (cb == 0 && threadIdx.x == 0) { st->numeric = 1; st->done = 1; }
@@ -453,18 +464,9 @@ __global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int G) {
     uint32_t* ex = p.excl + (int64_t)inst * p.inst_excl;
     ex[j >> 5] |= 1u << (j & 31);
     st->znorm2 += vmag2(zt);
-    st->iterations = p.t;
+    st->iterations = t;
   }
   if (cb == 0 && p.ord) tap_order_insert(p, inst, n, j);
-}
-
-int ls_split_groups(int t) {
-  const int n = t - 1;
-  if (n < 64) return 1;
-  int G = n / 24;
-  if (G < 2) G = 2;
-  if (G > LS_MAX_GROUPS) G = LS_MAX_GROUPS;
-  return G;
 }
 
 // Columns per thread of the w^H W product, rounded up to a power of two.
@@ -516,6 +518,29 @@ static hipError_t launch_ls_split(const LParams& p, int ninst, int G, int n, hip
   if ((e = launch_ls_by_kpt<FOURIER>(p, ninst, G, true, 0, n, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(ls_c_kernel<FOURIER>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
   return hipGetLastError();
+}
+
+hipError_t launch_ls_update_slots(const LParams& p, int ninst, int t_lo, int t_hi,
+                                  hipStream_t st) {
+  if (!p.tofs || t_lo < 1 || t_hi < t_lo || !p.wbuf || !p.vpart) return hipErrorInvalidValue;
+  const int n_hi = t_hi - 1;
+  if (n_hi > L_KPT * L_THREADS) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  // instances on the one-workgroup update (t <= 64), sized for the longest
+  if (ls_split_groups(t_lo) == 1) {
+    const int n1 = std::max(1, std::min(t_hi, 64) - 1);
+    const size_t wb = p.fourier ? 16 : 8;
+    const size_t lds = 2 * n1 * wb + (size_t)n1 * 4 + 16;
+    e = p.fourier ? launch_ls_by_kpt<true>(p, ninst, 1, false, lds, n1, st)
+                  : launch_ls_by_kpt<false>(p, ninst, 1, false, lds, n1, st);
+    if (e != hipSuccess) return e;
+  }
+  // instances on the split update, each with its own row split
+  const int G = ls_split_groups(t_hi);
+  if (G > 1)
+    e = p.fourier ? launch_ls_split<true>(p, ninst, G, n_hi, st)
+                  : launch_ls_split<false>(p, ninst, G, n_hi, st);
+  return e;
 }
 
 hipError_t launch_ls_update(const LParams& p, int ninst, hipStream_t st) {

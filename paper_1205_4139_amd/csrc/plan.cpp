@@ -41,7 +41,8 @@ RCParams rcorr_geometry(const fcmp_plan& P) {
 
 int rcorr_threads(const RCParams& q) { return std::min(256, std::max(64, q.B * q.L / 8)); }
 
-int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt) {
+int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
+              int tile) {
   if (n < 1) return set_error(FCMP_E_INVALID, "n must be >= 1");
   if (!probs) return set_error(FCMP_E_INVALID, "problems is NULL");
   if (!opt) return set_error(FCMP_E_INVALID, "options is NULL");
@@ -72,7 +73,7 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
   P.shape.omega = nullptr;
   P.opt = *opt;
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
-  P.g = make_geo(F, (int)P.shape.N, plan_tile(n));
+  P.g = make_geo(F, (int)P.shape.N, tile > 0 ? tile : plan_tile(n));
   P.wk = F ? V_C128 : V_F64;
   P.pk = opt->corr_precision == FCMP_FP32 ? (F ? V_C64 : V_F32) : P.wk;
   const int64_t N = P.shape.N, M = P.shape.M, K = P.shape.K;
@@ -407,7 +408,13 @@ int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
 // t-1 selected columns (direct while M_i (t-1) <= ratio N log2 N, per
 // instance, else through a forward transform of S_Lambda^T x) and the
 // transform of the zero-filled residual with the fused identification.
+static int conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st, const int32_t* tofs);
+
 int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
+  return conv_corr(P, t, npart, st, nullptr);
+}
+
+static int conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st, const int32_t* tofs) {
   const bool F = P.g.fourier;
   const int n = (int)P.n;
   const int N = (int)P.shape.N, M = (int)P.shape.M;
@@ -419,9 +426,11 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
     const int ntaps = t - 1;
     RCParams q = rcorr_geometry(P);
     q.lam = P.lam; q.x = P.x; q.ntaps = ntaps;
-    q.ord = P.ord + (ntaps & 1) * P.sK;
-    q.bstart = P.bst + (ntaps & 1) * P.sB;
+    q.ord = P.ord;
+    q.bstart = P.bst;
     q.inst_lam = P.sK; q.inst_x = P.sK; q.inst_ord = 2 * P.sK; q.inst_bstart = 2 * P.sB;
+    q.ord_half = P.sK; q.bstart_half = P.sB;
+    q.Kv = P.Kv; q.tofs = tofs;
     q.ent_k = P.ent_k; q.goff = P.cst; q.y = P.y_ent;
     q.inst_ent = P.sM; q.inst_goff = P.sCs; q.inst_y = P.sM;
     q.rscale = inv_sqrt_n;
@@ -443,6 +452,7 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
     *npart = transform_partials(P.pk, g, false);
     return FCMP_OK;
   }
+  if (tofs) return set_error(FCMP_E_INVALID, "slot iterations need the fused residual");
   const double thr = P.resid_ratio * (double)N * (double)g.logN;
   int64_t m_lo = P.hM[0], m_hi = P.hM[0];
   for (int32_t m : P.hM) { m_lo = std::min<int64_t>(m_lo, m); m_hi = std::max<int64_t>(m_hi, m); }
@@ -487,11 +497,9 @@ int plan_conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
   return FCMP_OK;
 }
 
-int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
-  int rc = plan_enqueue_prefix(P, opt, st);
-  if (rc) return rc;
+// Least-squares launch parameters of the plan (t and npart set by the caller).
+static LParams ls_params(const fcmp_plan& P) {
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
-  const int n = (int)P.n;
   const int N = (int)P.shape.N, K = (int)P.shape.K;
   const Geo& g = P.g;
   LParams lp{};
@@ -511,6 +519,16 @@ int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
     lp.nbuck = 1 << g.n2;
     lp.bshift = F ? 0 : g.n1;
   }
+  return lp;
+}
+
+int plan_enqueue(fcmp_plan& P, const fcmp_options& opt, hipStream_t st) {
+  int rc = plan_enqueue_prefix(P, opt, st);
+  if (rc) return rc;
+  const bool F = P.shape.matrix_class == FCMP_FOURIER;
+  const int n = (int)P.n;
+  const int N = (int)P.shape.N, K = (int)P.shape.K;
+  LParams lp = ls_params(P);
   lp.t = 1;
   {
     ProfScope ps(FCMP_PHASE_LS, st);
@@ -610,6 +628,196 @@ int plan_solve(fcmp_plan& P, const fcmp_options* o, const void* const* y, int32_
     }
     return plan_stats(n, hs.data(), ms, stats, phase_times ? pms : nullptr);
   }
+  return FCMP_OK;
+}
+
+// ---------------------------------------------------------------- slot plans
+
+int slot_tile() { return plan_tile(int64_t(1) << 30); }
+
+bool plan_slots_ok(const fcmp_problem& prob, const fcmp_options& opt) {
+  if (opt.algorithm != FCMP_OMP || opt.corr_method != FCMP_CORR_CONVENTIONAL ||
+      opt.res_tol > 0.0 || (opt.flags & FCMP_FLAG_PHASE_TIMES))
+    return false;
+  fcmp_plan P;
+  std::vector<int32_t> om((size_t)prob.M);
+  for (int64_t i = 0; i < prob.M; ++i) om[(size_t)i] = (int32_t)i;
+  fcmp_problem q = prob;
+  q.omega = om.data();
+  if (plan_init(P, 1, &q, &opt, slot_tile()) != FCMP_OK) return false;
+  return P.fused;
+}
+
+int plan_init_slots(fcmp_plan& P, int64_t n, const fcmp_problem& cap, const fcmp_options& opt) {
+  std::vector<int32_t> om((size_t)cap.M);
+  for (int64_t i = 0; i < cap.M; ++i) om[(size_t)i] = (int32_t)i;
+  fcmp_problem q = cap;
+  q.omega = om.data();
+  int rc = plan_init(P, 1, &q, &opt, slot_tile());
+  if (rc) return rc;
+  if (!P.fused) return set_error(FCMP_E_INVALID, "slot plans need the fused residual");
+  if (n < 1) return set_error(FCMP_E_INVALID, "n must be >= 1");
+  // n slots of the capacity shape, each with its own M and K
+  P.n = n;
+  P.hM.assign((size_t)n, (int32_t)cap.M);
+  P.hK.assign((size_t)n, (int32_t)cap.K);
+  P.uniform = false;
+  plan_layout(P, nullptr);
+  return FCMP_OK;
+}
+
+template <class T>
+static T* at(T* p, int64_t k) { return p ? p + k : nullptr; }
+static void* at_bytes(void* p, int64_t b) { return p ? (void*)((char*)p + b) : nullptr; }
+
+fcmp_plan plan_view(const fcmp_plan& P, int64_t s, int32_t M, int32_t K) {
+  fcmp_plan V;
+  V.n = 1;
+  V.shape = P.shape;
+  V.uniform = false;
+  V.hM.assign(1, M);
+  V.hK.assign(1, K);
+  V.opt = P.opt;
+  V.g = P.g;
+  V.wk = P.wk; V.pk = P.pk;
+  V.sM = P.sM; V.sN = P.sN; V.sK = P.sK; V.sW = P.sW; V.sG = P.sG; V.sG2 = P.sG2;
+  V.sP = P.sP; V.sE = P.sE; V.sB = P.sB; V.sC = P.sC; V.sCs = P.sCs;
+  V.resid_ratio = P.resid_ratio;
+  V.fused = P.fused; V.rreg = P.rreg;
+  V.npart = P.npart;
+  V.tw64 = P.tw64; V.tw32 = P.tw32;
+  const int64_t wb = vbytes(P.wk), pb = vbytes(P.pk);
+  V.ent_k = at(P.ent_k, s * P.sM);
+  V.perm = at(P.perm, s * P.sM);
+  V.goff = at(P.goff, s * P.sG);
+  if (!P.g.same_out) {
+    V.ent2_k = at(P.ent2_k, s * P.sM);
+    V.goff2 = at(P.goff2, s * P.sG2);
+    V.pos1 = at(P.pos1, s * P.sM);
+  } else {
+    V.ent2_k = V.ent_k;
+    V.goff2 = V.goff;
+    V.pos1 = nullptr;
+  }
+  V.cmask = at(P.cmask, s * P.sC);
+  V.cbase = at(P.cbase, s * P.sC);
+  V.cst = at(P.cst, s * P.sCs);
+  V.Mv = at(P.Mv, s);
+  V.Kv = at(P.Kv, s);
+  V.c64 = at_bytes(P.c64, s * P.sN * wb);
+  V.cp = P.cp == P.c64 ? V.c64 : at_bytes(P.cp, s * P.sN * pb);
+  V.ci16 = at(P.ci16, s * P.sN);
+  V.y_ent = at_bytes(P.y_ent, s * P.sM * wb);
+  V.r = at_bytes(P.r, s * P.sM * pb);
+  V.h0 = at_bytes(P.h0, s * P.sN * wb);
+  V.tmp = at_bytes(P.tmp, s * P.sN * wb);
+  V.partial = at(P.partial, s * P.sP);
+  V.lam = at(P.lam, s * P.sK);
+  V.ord = at(P.ord, s * 2 * P.sK);
+  V.bst = at(P.bst, s * 2 * P.sB);
+  V.excl = at(P.excl, s * P.sE);
+  V.x = at_bytes(P.x, s * P.sK * wb);
+  V.z = at_bytes(P.z, s * P.sK * wb);
+  V.W = at_bytes(P.W, s * P.sW * wb);
+  V.wbuf = at_bytes(P.wbuf, s * P.sK * wb);
+  V.vpart = at_bytes(P.vpart, s * ls_split_groups((int)P.shape.K) * P.sK * wb);
+  V.status = at(P.status, s);
+  V.dptrs = at(P.dptrs, 3 * s);
+  V.total = 0;
+  return V;
+}
+
+int plan_upload_twiddles(fcmp_plan& P, const HostTables& t, hipStream_t st, const StageFn& stage) {
+  if (t.tw64.size() != (size_t)tw_count(P.g)) return set_error(FCMP_E_INVALID, "twiddle geometry");
+  const size_t b64 = t.tw64.size() * sizeof(double2), b32 = t.tw32.size() * sizeof(float2);
+  HIP_TRY(hipMemcpyAsync(P.tw64, stage ? stage(t.tw64.data(), b64) : t.tw64.data(), b64,
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(P.tw32, stage ? stage(t.tw32.data(), b32) : t.tw32.data(), b32,
+                         hipMemcpyHostToDevice, st));
+  return FCMP_OK;
+}
+
+int plan_upload_tables(fcmp_plan& V, const HostTables& t, hipStream_t st, const StageFn& stage) {
+  const size_t M = (size_t)V.hM[0];
+  if (t.ent_k.size() < M || t.goff.size() > (size_t)V.sG ||
+      (V.rreg && t.cmask.size() > (size_t)V.sC) || (V.cst && t.cst.size() > (size_t)V.sCs) ||
+      (!V.g.same_out && t.goff2.size() > (size_t)V.sG2))
+    return set_error(FCMP_E_INVALID, "tables do not match the slot");
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (!bytes) return hipSuccess;
+    const void* from = stage ? stage(src, bytes) : src;
+    return hipMemcpyAsync(dst, from, bytes, hipMemcpyHostToDevice, st);
+  };
+  HIP_TRY(up(V.ent_k, t.ent_k.data(), M * 4));
+  HIP_TRY(up(V.perm, t.perm.data(), M * 4));
+  HIP_TRY(up(V.goff, t.goff.data(), t.goff.size() * 4));
+  if (!V.g.same_out) {
+    HIP_TRY(up(V.ent2_k, t.ent2_k.data(), M * 4));
+    HIP_TRY(up(V.goff2, t.goff2.data(), t.goff2.size() * 4));
+    HIP_TRY(up(V.pos1, t.pos1.data(), M * 4));
+  }
+  if (V.rreg) {
+    HIP_TRY(up(V.cmask, t.cmask.data(), t.cmask.size() * 4));
+    HIP_TRY(up(V.cbase, t.cbase.data(), t.cbase.size() * 4));
+  }
+  if (V.cst) HIP_TRY(up(V.cst, t.cst.data(), t.cst.size() * 4));
+  return plan_kernel_vector(V, st);
+}
+
+int plan_copy_tables(fcmp_plan& V, const fcmp_plan& from, hipStream_t st) {
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    return (dst && src && dst != src)
+               ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st)
+               : hipSuccess;
+  };
+  const size_t M = (size_t)V.hM[0];
+  const size_t wb = vbytes(V.wk), pb = vbytes(V.pk);
+  HIP_TRY(cp(V.ent_k, from.ent_k, M * 4));
+  HIP_TRY(cp(V.perm, from.perm, M * 4));
+  HIP_TRY(cp(V.goff, from.goff, (size_t)V.sG * 4));
+  if (!V.g.same_out) {
+    HIP_TRY(cp(V.ent2_k, from.ent2_k, M * 4));
+    HIP_TRY(cp(V.goff2, from.goff2, (size_t)V.sG2 * 4));
+    HIP_TRY(cp(V.pos1, from.pos1, M * 4));
+  }
+  HIP_TRY(cp(V.cmask, from.cmask, (size_t)V.sC * 4));
+  HIP_TRY(cp(V.cbase, from.cbase, (size_t)V.sC * 4));
+  HIP_TRY(cp(V.cst, from.cst, (size_t)V.sCs * 4));
+  HIP_TRY(cp(V.c64, from.c64, (size_t)V.shape.N * wb));
+  if (V.cp != V.c64) HIP_TRY(cp(V.cp, from.cp, (size_t)V.shape.N * pb));
+  HIP_TRY(cp(V.ci16, from.ci16, (size_t)V.shape.N * 2));
+  return FCMP_OK;
+}
+
+int plan_join(fcmp_plan& V, const fcmp_options& opt, hipStream_t st) {
+  int rc = plan_enqueue_prefix(V, opt, st);
+  if (rc) return rc;
+  LParams lp = ls_params(V);
+  lp.t = 1;
+  HIP_TRY(launch_ls_update(lp, 1, st));
+  return FCMP_OK;
+}
+
+int plan_step_slots(fcmp_plan& P, int step, const int32_t* tofs, int t_lo, int t_hi,
+                    hipStream_t st) {
+  if (!tofs || t_lo < 2 || t_hi < t_lo || t_hi > P.shape.K)
+    return set_error(FCMP_E_INVALID, "slot step out of range");
+  int npart = 0;
+  int rc = conv_corr(P, step, &npart, st, tofs);
+  if (rc) return rc;
+  LParams lp = ls_params(P);
+  lp.t = step;
+  lp.tofs = tofs;
+  lp.npart = npart;
+  HIP_TRY(launch_ls_update_slots(lp, (int)P.n, t_lo, t_hi, st));
+  return FCMP_OK;
+}
+
+int plan_finish(fcmp_plan& V, hipStream_t st) {
+  HIP_TRY(launch_finalize_ptr(V.g.fourier, V.status, V.lam, V.x, (int)V.shape.K, V.sK, V.sK,
+                              (int32_t* const*)(V.dptrs + 1), (void* const*)(V.dptrs + 2), 1, st,
+                              V.Kv));
+  HIP_TRY(launch_status_done(V.status, 1, st));
   return FCMP_OK;
 }
 

@@ -1,6 +1,7 @@
 // Plans: Omega-derived tables, the kernel vector and per-solve buffers for n
 // problems of one shape, solved in lockstep.
 #pragma once
+#include <functional>
 #include <vector>
 
 #include "engine.h"
@@ -78,7 +79,9 @@ namespace fcmp {
 
 // Lays out the plan's buffers from base (nullptr: sizes only).
 void plan_layout(fcmp_plan& P, char* base);
-int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt);
+// tile: transform tile (0: plan_tile(n)); it never changes a result.
+int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
+              int tile = 0);
 int plan_build(fcmp_plan& P, const fcmp_problem* probs, hipStream_t st);
 // timed = false: stats (when given) carry no device time (ms_total = 0) and
 // no hipEvent is created.
@@ -107,6 +110,40 @@ int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats,
                const double* phase_ms = nullptr);
 // Per-solve phase times (ms per FCMP_PHASE_*) into the stats fields.
 void stats_phases(fcmp_stats& s, const double* phase_ms);
+// ---- slot plans (continuous batching)
+// n slots of one (class, N) and options, sized for M <= cap.M and K <= cap.K;
+// requests join a free slot and leave it between iterations, and slot s runs
+// iteration step - tofs[s] of its own solve (tofs on the device).  Every
+// slot starts done.  Only OMP with the conventional correlation fused with
+// the residual (plan_slots_ok) runs this way.
+bool plan_slots_ok(const fcmp_problem& prob, const fcmp_options& opt);
+int plan_init_slots(fcmp_plan& P, int64_t n, const fcmp_problem& cap, const fcmp_options& opt);
+// The transform tile of every slot plan (tables are built for its geometry).
+int slot_tile();
+// One-instance view of slot s: every per-instance buffer offset to the slot;
+// dptrs points at the slot's three device pointers (y, support, x).
+fcmp_plan plan_view(const fcmp_plan& P, int64_t s, int32_t M, int32_t K);
+// stage (nullable) returns a pinned copy of host bytes to copy from, which
+// must stay unchanged until the stream has run the copy.
+using StageFn = std::function<const void*(const void*, size_t)>;
+int plan_upload_twiddles(fcmp_plan& P, const HostTables& t, hipStream_t st,
+                         const StageFn& stage = nullptr);
+// The view's Omega tables from host tables built for its problem (slot_tile
+// geometry), then its kernel vector; or the tables and kernel vector of
+// another slot's view.
+int plan_upload_tables(fcmp_plan& V, const HostTables& t, hipStream_t st,
+                       const StageFn& stage = nullptr);
+int plan_copy_tables(fcmp_plan& V, const fcmp_plan& from, hipStream_t st);
+// The view's first iteration: exclusions, y in entry order, status, h_0 with
+// the first identification and the t = 1 update (its y at dptrs[0]).
+int plan_join(fcmp_plan& V, const fcmp_options& opt, hipStream_t st);
+// One iteration of every slot that is not done: the fused conventional
+// correlation and the update, t_lo .. t_hi spanning the slots' iterations.
+int plan_step_slots(fcmp_plan& P, int step, const int32_t* tofs, int t_lo, int t_hi,
+                    hipStream_t st);
+// The view's support and x to its output pointers; then the slot is done.
+int plan_finish(fcmp_plan& V, hipStream_t st);
+
 // SP / CoSaMP for every instance of the plan (after h_0 is in place)
 int plan_solve_set(fcmp_plan& P, const fcmp_options& opt, int32_t* const* sup, void* const* xo,
                    fcmp_stats* stats, hipStream_t st);

@@ -52,14 +52,15 @@ __global__ void __launch_bounds__(256) rcorr_kernel(RCParams p) {
   VC* twhi = twlo + nlo;
   const uint32_t maskN = (uint32_t)p.N - 1u;
   const uint32_t mask1 = (1u << p.logN1) - 1u;
-  const int ntaps = p.ntaps;
+  const int ntaps = p.tofs ? p.ntaps - p.tofs[inst] : p.ntaps;
+  if (p.Kv && ntaps >= p.Kv[inst]) return;   // its K selections are made
 
   // The loads of the taps (first chunk, in bucket order) and of the bucket
   // starts are issued together, before any of them is waited for.  (The rows
   // of Omega are loaded after the FP64 transform: values held in registers
   // across it would cost occupancy.)
-  const int32_t* bs = p.bstart + (int64_t)inst * p.inst_bstart;
-  const int32_t* od = p.ord + (int64_t)inst * p.inst_ord;
+  const int32_t* bs = p.bstart + (int64_t)inst * p.inst_bstart + (ntaps & 1) * p.bstart_half;
+  const int32_t* od = p.ord + (int64_t)inst * p.inst_ord + (ntaps & 1) * p.ord_half;
   const int32_t* lm = p.lam + (int64_t)inst * p.inst_lam;
   const VR* xs = (const VR*)p.x + (int64_t)inst * p.inst_x;
   int32_t* bsl = tl + nt;   // bucket starts in LDS (L + 1)

@@ -50,7 +50,8 @@ rcorr_reg_kernel(RCParams p) {
   const uint32_t maskN = (uint32_t)p.N - 1u;
   const uint32_t mask1 = (1u << p.logN1) - 1u;
   const int dsh = p.logN1 - 8;        // W_256^q = W_N1^(q << dsh)
-  const int ntaps = p.ntaps;
+  const int ntaps = p.tofs ? p.ntaps - p.tofs[inst] : p.ntaps;
+  if (p.Kv && ntaps >= p.Kv[inst]) return;   // its K selections are made
 
   // LDS: region A (staged taps; then the exchange buffers; then the output
   // tile), then the inter-pass twiddles of the correlation precision
@@ -70,8 +71,8 @@ rcorr_reg_kernel(RCParams p) {
   // Global loads with no dependence on this workgroup's LDS are issued first,
   // so their latencies overlap: the first chunk of taps, the tables, the
   // column masks of the residual and the per-register twiddle factors.
-  const int32_t* bs = p.bstart + (int64_t)inst * p.inst_bstart;
-  const int32_t* od = p.ord + (int64_t)inst * p.inst_ord;
+  const int32_t* bs = p.bstart + (int64_t)inst * p.inst_bstart + (ntaps & 1) * p.bstart_half;
+  const int32_t* od = p.ord + (int64_t)inst * p.inst_ord + (ntaps & 1) * p.ord_half;
   const int32_t* lm = p.lam + (int64_t)inst * p.inst_lam;
   const VR* xs = (const VR*)p.x + (int64_t)inst * p.inst_x;
   int tlv0 = 0;

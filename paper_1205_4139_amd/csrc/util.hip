@@ -102,6 +102,17 @@ hipError_t launch_finalize(int fourier, const Status* status, const int32_t* lam
   return hipGetLastError();
 }
 
+__global__ void status_done_kernel(Status* s, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) s[i].done = 1;
+}
+
+hipError_t launch_status_done(Status* s, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(status_done_kernel, dim3((n + 255) / 256), dim3(256), 0, st, s, n);
+  return hipGetLastError();
+}
+
 __global__ void reduce_sel_kernel(const Sel* partial, int n, Sel* out) {
   __shared__ Sel red[16];
   double bk = -1.0, bk2 = -1.0;

@@ -32,7 +32,7 @@ def test_header_symbols_exported(fc):
 
 
 def test_abi_version_and_status(fc):
-    assert fc.lib.fcmp_abi_version() == 2
+    assert fc.lib.fcmp_abi_version() == 3
     assert fc.lib.fcmp_status_str(0) == b"ok"
     assert fc.lib.fcmp_status_str(-2) == b"workspace too small"
 

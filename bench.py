@@ -437,6 +437,32 @@ def per_t_leg(fc, device):
     return out
 
 
+def serve_bound(count: int = 4000):
+    """HBM-bound ceiling of the serving mix: mean algorithmic bytes per
+    request of the slot path over `count` draws of the stream's (class, N, M,
+    K) law, and the request rate that moves them at the HBM peak.  Per OMP
+    iteration t: the correlation reads r (complex64 / FP32) and Omega and
+    writes h (M s + 4M + N s); the least-squares update reads the packed FP64
+    inverse factor twice (w = W g, then w^H W: 2 (t-1) t / 2 entries)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(5000))
+    tot = ls = 0.0
+    for _ in range(count):
+        F = rng.integers(0, 2) == 1
+        N = 1 << int(rng.integers(12, 19))
+        Mi = int(rng.integers(N // 8, N // 4 + 1))
+        Ki = int(rng.integers(16, Mi // 16 + 1))
+        s, wb = (8, 16) if F else (4, 8)
+        corr = Ki * (Mi * s + 4 * Mi + N * s)
+        n = Ki - 1
+        lsb = wb * n * (n + 1) * (n + 2) / 3.0   # sum over t of 2 * (t-1) t / 2 entries
+        tot += corr + lsb
+        ls += lsb
+    mean = tot / count
+    return {"mean_bytes_per_request": round(mean), "least_squares_share": round(ls / tot, 3),
+            "hbm_bound_req_per_s": round(HBM_PEAK_GBS * 1e9 / mean, 1)}
+
+
 def serve_sweep(fc, device, rates, seconds: float):
     """The serving stream at increasing offered rates (each `seconds` of
     arrivals); stops after the first rate whose completion rate over the
@@ -453,6 +479,7 @@ def serve_sweep(fc, device, rates, seconds: float):
             break
         sustained = r
     return {"runs": runs,
+            "bound": serve_bound(),
             "sustained_req_per_s": sustained["offered_req_per_s"] if sustained else None,
             "at_sustained": ({k: sustained[k] for k in ("completed_in_window_per_s", "latency_ms",
                                                          "queue_ms")} if sustained else None),

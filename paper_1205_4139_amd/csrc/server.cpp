@@ -108,13 +108,14 @@ class TableCache {
 };
 
 // Slot capacities of the group a request would create: M up to the smallest
-// of N/4, N/2, N that holds it; K up to the smallest of 256, 1024, 4096 (and
-// so on) that holds it.
+// of N/4, N/2, N that holds it; K up to N/64 (clamped to 256 .. 4096), or the
+// next power of two that holds the request's K, so that one group per
+// (class, N) usually takes every sparsity of a stream.
 void slot_caps(const fcmp_problem& p, int64_t* Mcap, int64_t* Kcap) {
   int64_t m = p.N / 4;
   while (m < p.M) m *= 2;
-  int64_t k = 256;
-  while (k < p.K) k *= 4;
+  int64_t k = std::min<int64_t>(4096, std::max<int64_t>(256, p.N / 64));
+  while (k < p.K) k *= 2;
   *Mcap = std::min<int64_t>(m, p.N);
   *Kcap = std::min<int64_t>(k, *Mcap - 1);
 }

@@ -376,14 +376,60 @@ int fcmp_corr_curve_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
 int fcmp_corr_curve(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
                     int32_t batch, const int32_t* ts, int32_t nt, void* ws_dev, size_t ws_bytes,
                     float* fast_ms, float* conv_ms, void* hip_stream);
-/* Loads every valid entry of a cache file into the table (host-only);
- * FCMP_E_NOTFOUND when the file is missing or holds no valid entry. */
+/* Loads every valid entry of a cache file (switch iterations and launch
+ * schedules) into the tables (host-only); FCMP_E_NOTFOUND when the file is
+ * missing or holds no valid entry. */
 int fcmp_autotune_load(const char* cache_path);
 /* The switch iteration an adaptive solve with switch_t = 0 uses; *tuned
  * (nullable) is 1 when it comes from the table, 0 for the flop model.
  * Host-only. */
 int fcmp_adaptive_switch(int32_t matrix_class, int64_t N, int32_t corr_precision,
                          int32_t* switch_t, int32_t* tuned);
+
+/* ---- launch-schedule autotuning --------------------------------------- */
+
+/* How a plan spreads its transforms over the device: the values per
+ * workgroup tile of the two-pass transforms (the B1, B2 sequences per
+ * workgroup of the N = N1 N2 split), the most threads of a transform
+ * workgroup, and the threads of the generic fused residual + first pass.
+ * Zero fields mean the library's defaults.  No field changes a result: each
+ * one only splits the same per-element arithmetic and the identification's
+ * total order over workgroups and threads differently.  (The least-squares
+ * row split and the persistent kernel's workgroup size are not schedule
+ * fields: they fix the order of floating-point sums.) */
+typedef struct {
+  int32_t tile;       /* power of two <= 8192 (0: chosen from the batch size) */
+  int32_t threads;    /* 64, 128 or 256 (0: 256) */
+  int32_t rthreads;   /* 64, 128 or 256 (0: from the first pass's tile) */
+} fcmp_schedule;
+/* fcmp_schedule_tune times, for a lockstep plan of `batch` problems (class,
+ * N, M) in the workspace (bytes from fcmp_schedule_query_workspace,
+ * host-only), one conventional correlation (t = 16) plus the share of the
+ * h_0 and kernel-vector transforms of a 256-iteration solve under the
+ * default schedule and under every distinct tile, then thread counts at the
+ * best tile, and records the fastest in the library's table for (device
+ * architecture, class, N, precision, batch bucket: 1, <= 8, <= 32, <= 128,
+ * more); plans and batch plans created afterwards for that key use it.
+ * ms_default / ms_best (nullable) receive the timed costs.  cache_path
+ * (nullable): the same text file as fcmp_autotune, one
+ * "sched arch class N precision bucket tile threads rthreads" line per
+ * entry; an entry found there is used without measuring, a new one is
+ * appended.  The call synchronises the stream. */
+int fcmp_schedule_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
+                                  int32_t corr_precision, int32_t batch, size_t* bytes);
+int fcmp_schedule_tune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
+                       int32_t batch, const char* cache_path, void* ws_dev, size_t ws_bytes,
+                       fcmp_schedule* best, float* ms_default, float* ms_best,
+                       void* hip_stream);
+/* Sets (s non-NULL) or drops (s NULL) the table entry for the current
+ * device's architecture and (class, N, precision, batch bucket). */
+int fcmp_schedule_set(int32_t matrix_class, int64_t N, int32_t corr_precision, int32_t batch,
+                      const fcmp_schedule* s);
+/* The schedule a plan of `batch` problems of (class, N, precision) uses;
+ * *tuned (nullable) is 1 when it comes from the table.  Host-only while the
+ * table is empty. */
+int fcmp_schedule_get(int32_t matrix_class, int64_t N, int32_t corr_precision, int32_t batch,
+                      fcmp_schedule* s, int32_t* tuned);
 
 /* ---- phase timing ------------------------------------------------------ */
 

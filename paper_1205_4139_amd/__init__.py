@@ -91,6 +91,10 @@ class ServerInfo(ctypes.Structure):
                 ("tables_copied", ctypes.c_int64)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("threads", ctypes.c_int32), ("rthreads", ctypes.c_int32)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("ms", ctypes.c_double * NPHASE), ("launches", ctypes.c_int64 * NPHASE)]
 
@@ -121,6 +125,13 @@ def _load():
         "fcmp_autotune": ([i32, i64, i64, i32, i32, ctypes.c_char_p, vp, sz,
                            ctypes.POINTER(i32), vp], ctypes.c_int),
         "fcmp_autotune_load": ([ctypes.c_char_p], ctypes.c_int),
+        "fcmp_schedule_query_workspace": ([i32, i64, i64, i32, i32, ctypes.POINTER(sz)], ctypes.c_int),
+        "fcmp_schedule_tune": ([i32, i64, i64, i32, i32, ctypes.c_char_p, vp, sz,
+                                ctypes.POINTER(Schedule), ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_float), vp], ctypes.c_int),
+        "fcmp_schedule_set": ([i32, i64, i32, i32, ctypes.POINTER(Schedule)], ctypes.c_int),
+        "fcmp_schedule_get": ([i32, i64, i32, i32, ctypes.POINTER(Schedule),
+                               ctypes.POINTER(i32)], ctypes.c_int),
         "fcmp_corr_curve_query_workspace": ([i32, i64, i64, i32, i32, i32, ctypes.POINTER(sz)],
                                             ctypes.c_int),
         "fcmp_corr_curve": ([i32, i64, i64, i32, i32, ctypes.POINTER(i32), i32, vp, sz,
@@ -604,6 +615,39 @@ def corr_curve(cls, N, M, ts, precision="fp32", batch=1, device="cuda"):
     _check(lib.fcmp_corr_curve(CLASS[cls], int(N), int(M), PREC[precision], int(batch), ta,
                                len(ts), _ptr(ws), ws.numel(), fa, ca, _stream()))
     return list(fa), list(ca)
+
+
+def schedule_tune(cls, N, M, precision="fp32", batch=8, cache_path=None, device="cuda") -> dict:
+    """Times launch schedules (transform tile, thread counts) for a lockstep
+    plan of `batch` problems (class, N, M) and records the fastest for plans
+    of that shape; returns it with the default's and its timed cost."""
+    nb = ctypes.c_size_t(0)
+    _check(lib.fcmp_schedule_query_workspace(CLASS[cls], int(N), int(M), PREC[precision],
+                                             int(batch), ctypes.byref(nb)))
+    ws = _workspace(nb.value, device)
+    best, a, b = Schedule(), ctypes.c_float(0), ctypes.c_float(0)
+    _check(lib.fcmp_schedule_tune(CLASS[cls], int(N), int(M), PREC[precision], int(batch),
+                                  cache_path.encode() if cache_path else None, _ptr(ws),
+                                  ws.numel(), ctypes.byref(best), ctypes.byref(a), ctypes.byref(b),
+                                  _stream()))
+    return {"tile": best.tile, "threads": best.threads, "rthreads": best.rthreads,
+            "ms_default": a.value, "ms_best": b.value}
+
+
+def schedule_set(cls, N, precision="fp32", batch=1, tile=0, threads=0, rthreads=0, drop=False):
+    """Sets (or drops) the schedule plans of (class, N, precision, batch
+    bucket) use on the current device."""
+    s = Schedule(int(tile), int(threads), int(rthreads))
+    _check(lib.fcmp_schedule_set(CLASS[cls], int(N), PREC[precision], int(batch),
+                                 None if drop else ctypes.byref(s)))
+
+
+def schedule_get(cls, N, precision="fp32", batch=1) -> dict:
+    """The schedule a plan of `batch` problems of (class, N, precision) uses."""
+    s, tuned = Schedule(), ctypes.c_int32(0)
+    _check(lib.fcmp_schedule_get(CLASS[cls], int(N), PREC[precision], int(batch), ctypes.byref(s),
+                                 ctypes.byref(tuned)))
+    return {"tile": s.tile, "threads": s.threads, "rthreads": s.rthreads, "tuned": bool(tuned.value)}
 
 
 def autotune_load(cache_path) -> None:

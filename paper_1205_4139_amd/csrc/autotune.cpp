@@ -1,4 +1,5 @@
-// Autotuner for the adaptive correlation method.
+// Autotuners: the adaptive correlation method's switch iteration, and the
+// launch schedule (transform tile and thread counts) of a plan shape.
 //
 // The paper's adaptive strategy runs the fast method while it is cheaper
 // than the conventional one and switches afterwards; Table I's flop counts
@@ -91,12 +92,12 @@ struct CurveBench {
 };
 
 int curve_setup(CurveBench& C, int32_t cls, int64_t N, int64_t M, int32_t prec, int32_t batch,
-                int32_t tmax, void* ws_dev, size_t ws_bytes, hipStream_t st) {
+                int32_t tmax, void* ws_dev, size_t ws_bytes, hipStream_t st, int tile = 0) {
   fcmp_options opt;
   int rc = tune_shape(cls, N, M, batch, tmax, C.om, C.probs, opt, prec);
   if (rc) return rc;
   fcmp_plan& P = C.P;
-  if ((rc = plan_init(P, batch, C.probs.data(), &opt))) return rc;
+  if ((rc = plan_init(P, batch, C.probs.data(), &opt, tile))) return rc;
   if (!ws_dev) return set_error(FCMP_E_INVALID, "workspace is NULL");
   if (ws_bytes < P.total) return set_error(FCMP_E_WORKSPACE, "workspace too small");
   C.st = st;
@@ -150,9 +151,207 @@ int curve_point(CurveBench& C, int t, float* fast_ms, float* conv_ms) {
   return FCMP_OK;
 }
 
+// ---- launch schedules
+
+constexpr int kSchedT = 16;   // the conventional correlation is timed at t = 16
+
+// Tiles worth timing for N: each distinct (B1, B2) split once.
+std::vector<int> sched_tiles(bool F, int64_t N) {
+  std::vector<int> out;
+  std::vector<std::pair<int, int>> seen;
+  for (int tile = 256; tile <= 8192; tile *= 2) {
+    const Geo g = make_geo(F, (int)N, tile);
+    const std::pair<int, int> k(g.B1, g.B2);
+    if (std::find(seen.begin(), seen.end(), k) != seen.end()) continue;
+    seen.push_back(k);
+    out.push_back(tile);
+    if (!g.grouped) break;   // one workgroup per transform: no tile to choose
+  }
+  return out;
+}
+
+// Device time of one solve's transform work per iteration under the plan's
+// schedule: a conventional correlation at t = kSchedT, plus the kernel vector
+// and h_0 transforms spread over 255 iterations (both FP64 forward transforms
+// of a sparse input; the kernel vector's stands for both).
+int sched_cost(CurveBench& C, float* ms) {
+  fcmp_plan& P = C.P;
+  hipStream_t st = C.st;
+  int npart = 0, rc;
+  if ((rc = plan_set_tap_order(P, C.lam.data(), kSchedT - 1, st, C.hord, C.hbst))) return rc;
+  if ((rc = plan_conv_corr(P, kSchedT, &npart, st)) || (rc = plan_kernel_vector(P, st))) return rc;
+  HIP_TRY(hipEventRecord(C.e[0], st));
+  for (int r = 0; r < kReps; ++r)
+    if ((rc = plan_conv_corr(P, kSchedT, &npart, st))) return rc;
+  HIP_TRY(hipEventRecord(C.e[1], st));
+  for (int r = 0; r < kReps; ++r)
+    if ((rc = plan_kernel_vector(P, st))) return rc;
+  HIP_TRY(hipEventRecord(C.e[2], st));
+  HIP_TRY(hipEventSynchronize(C.e[2]));
+  float a = 0.f, b = 0.f;
+  HIP_TRY(hipEventElapsedTime(&a, C.e[0], C.e[1]));
+  HIP_TRY(hipEventElapsedTime(&b, C.e[1], C.e[2]));
+  *ms = a / kReps + (b / kReps) * 2.0f / 255.0f;
+  return FCMP_OK;
+}
+
+int sched_args(int32_t cls, int64_t N, int64_t M, int32_t prec, int32_t batch) {
+  if (cls != FCMP_HADAMARD && cls != FCMP_FOURIER) return set_error(FCMP_E_INVALID, "bad class");
+  if (N < 64 || (N & (N - 1)) != 0 || N > (int64_t(1) << 24))
+    return set_error(FCMP_E_INVALID, "N must be a power of two in [64, 2^24]");
+  if (M <= kSchedT || M > N) return set_error(FCMP_E_INVALID, "M must be in (16, N]");
+  if (prec != FCMP_FP32 && prec != FCMP_FP64) return set_error(FCMP_E_INVALID, "bad precision");
+  if (batch < 1 || batch > 4096) return set_error(FCMP_E_INVALID, "batch must be in [1, 4096]");
+  return FCMP_OK;
+}
+
+std::string g_sched_line(const std::string& arch, int cls, int64_t N, int prec, int bucket,
+                         const Sched& s) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "sched %s %d %lld %d %d %d %d %d\n", arch.c_str(), cls,
+                (long long)N, prec, bucket, s.tile, s.threads, s.rthreads);
+  return buf;
+}
+
 }  // namespace
 
 extern "C" {
+
+int fcmp_schedule_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
+                                  int32_t corr_precision, int32_t batch, size_t* bytes) {
+  if (!bytes) return set_error(FCMP_E_INVALID, "bytes is NULL");
+  int rc = sched_args(matrix_class, N, M, corr_precision, batch);
+  if (rc) return rc;
+  size_t most = 0;
+  for (int tile : sched_tiles(matrix_class == FCMP_FOURIER, N)) {
+    std::vector<int32_t> om;
+    std::vector<fcmp_problem> probs;
+    fcmp_options opt;
+    if ((rc = tune_shape(matrix_class, N, M, batch, kSchedT + 1, om, probs, opt, corr_precision)))
+      return rc;
+    fcmp_plan P;
+    if ((rc = plan_init(P, batch, probs.data(), &opt, tile))) return rc;
+    most = std::max(most, P.total);
+  }
+  *bytes = most;
+  return FCMP_OK;
+}
+
+int fcmp_schedule_tune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
+                       int32_t batch, const char* cache_path, void* ws_dev, size_t ws_bytes,
+                       fcmp_schedule* best, float* ms_default, float* ms_best, void* hip_stream) {
+  if (!best) return set_error(FCMP_E_INVALID, "best is NULL");
+  int rc = sched_args(matrix_class, N, M, corr_precision, batch);
+  if (rc) return rc;
+  const std::string arch = device_arch();
+  const int bucket = batch_bucket(batch);
+  if (cache_path && fcmp_autotune_load(cache_path) == FCMP_OK) {
+    Sched s;
+    if (tuned_sched(matrix_class, N, corr_precision, batch, &s)) {
+      *best = fcmp_schedule{s.tile, s.threads, s.rthreads};
+      if (ms_default) *ms_default = 0.f;
+      if (ms_best) *ms_best = 0.f;
+      return FCMP_OK;
+    }
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  const bool F = matrix_class == FCMP_FOURIER;
+  // the default schedule first, then every tile at default threads
+  float t_def = 0.f;
+  {
+    CurveBench C;
+    if ((rc = curve_setup(C, matrix_class, N, M, corr_precision, batch, kSchedT + 1, ws_dev,
+                          ws_bytes, st, plan_tile(batch))) ||
+        (rc = sched_cost(C, &t_def)))
+      return rc;
+  }
+  float t_best = 1e30f;
+  int tile_best = plan_tile(batch);
+  for (int tile : sched_tiles(F, N)) {
+    CurveBench C;
+    float t = 0.f;
+    if ((rc = curve_setup(C, matrix_class, N, M, corr_precision, batch, kSchedT + 1, ws_dev,
+                          ws_bytes, st, tile)) ||
+        (rc = sched_cost(C, &t)))
+      return rc;
+    if (t < t_best) { t_best = t; tile_best = tile; }
+  }
+  // thread counts at the best tile (neither changes the tables)
+  CurveBench C;
+  if ((rc = curve_setup(C, matrix_class, N, M, corr_precision, batch, kSchedT + 1, ws_dev,
+                        ws_bytes, st, tile_best)))
+    return rc;
+  Sched sb;
+  sb.tile = tile_best;
+  for (int th : {64, 128, 256}) {
+    float t = 0.f;
+    if (plan_set_threads(C.P, th, 0) != FCMP_OK) continue;
+    if ((rc = sched_cost(C, &t))) return rc;
+    if (t < t_best) { t_best = t; sb.threads = th; }
+  }
+  if (C.P.fused && !C.P.rreg) {
+    for (int rt : {64, 128, 256}) {
+      float t = 0.f;
+      if (plan_set_threads(C.P, sb.threads, rt) != FCMP_OK) continue;
+      if ((rc = sched_cost(C, &t))) return rc;
+      if (t < t_best) { t_best = t; sb.rthreads = rt; }
+    }
+  }
+  if (t_def <= t_best) {   // nothing beat the defaults: record them
+    sb = Sched{};
+    sb.tile = plan_tile(batch);
+    t_best = t_def;
+  }
+  set_tuned_sched(arch, matrix_class, N, corr_precision, bucket, sb);
+  *best = fcmp_schedule{sb.tile, sb.threads, sb.rthreads};
+  if (ms_default) *ms_default = t_def;
+  if (ms_best) *ms_best = t_best;
+  if (cache_path) {
+    FILE* f = std::fopen(cache_path, "a");
+    if (!f) return set_error(FCMP_E_INVALID, "cannot append to the cache file");
+    std::fputs(g_sched_line(arch, matrix_class, N, corr_precision, bucket, sb).c_str(), f);
+    std::fclose(f);
+  }
+  return FCMP_OK;
+}
+
+int fcmp_schedule_set(int32_t matrix_class, int64_t N, int32_t corr_precision, int32_t batch,
+                      const fcmp_schedule* s) {
+  if (matrix_class != FCMP_HADAMARD && matrix_class != FCMP_FOURIER)
+    return set_error(FCMP_E_INVALID, "bad class");
+  if (N < 2 || (N & (N - 1)) != 0) return set_error(FCMP_E_INVALID, "N must be a power of two");
+  if (batch < 1) return set_error(FCMP_E_INVALID, "batch must be >= 1");
+  const std::string arch = device_arch();
+  if (!s) {
+    erase_tuned_sched(arch, matrix_class, N, corr_precision, batch_bucket(batch));
+    return FCMP_OK;
+  }
+  if (s->tile < 0 || s->tile > 8192 || (s->tile & (s->tile - 1)) ||
+      (s->threads != 0 && s->threads != 64 && s->threads != 128 && s->threads != 256) ||
+      (s->rthreads != 0 && s->rthreads != 64 && s->rthreads != 128 && s->rthreads != 256))
+    return set_error(FCMP_E_INVALID, "tile must be a power of two <= 8192, threads 64/128/256");
+  set_tuned_sched(arch, matrix_class, N, corr_precision, batch_bucket(batch),
+                  Sched{s->tile, s->threads, s->rthreads});
+  return FCMP_OK;
+}
+
+int fcmp_schedule_get(int32_t matrix_class, int64_t N, int32_t corr_precision, int32_t batch,
+                      fcmp_schedule* s, int32_t* tuned) {
+  if (!s) return set_error(FCMP_E_INVALID, "s is NULL");
+  if (batch < 1) return set_error(FCMP_E_INVALID, "batch must be >= 1");
+  std::vector<int32_t> om;
+  std::vector<fcmp_problem> probs;
+  fcmp_options opt;
+  int rc = tune_shape(matrix_class, N, std::max<int64_t>(2, N / 4), batch, 2, om, probs, opt,
+                      corr_precision);
+  if (rc) return rc;
+  fcmp_plan P;
+  if ((rc = plan_init(P, batch, probs.data(), &opt))) return rc;
+  const Sched d = plan_sched(P);
+  *s = fcmp_schedule{d.tile, d.threads, d.rthreads};
+  if (tuned) *tuned = P.sched_tuned ? 1 : 0;
+  return FCMP_OK;
+}
 
 int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
                   int32_t batch, const char* cache_path, void* ws_dev, size_t ws_bytes,
@@ -229,14 +428,28 @@ int fcmp_autotune_load(const char* cache_path) {
   if (!cache_path) return set_error(FCMP_E_INVALID, "cache_path is NULL");
   FILE* f = std::fopen(cache_path, "r");
   if (!f) return set_error(FCMP_E_NOTFOUND, "no cache file");
-  int cls = 0, prec = 0, t = 0;
-  long long N = 0;
   int n = 0;
-  while (std::fscanf(f, "%d %lld %d %d", &cls, &N, &prec, &t) == 4) {
-    if ((cls == FCMP_HADAMARD || cls == FCMP_FOURIER) && N >= 2 && (N & (N - 1)) == 0 &&
-        (prec == FCMP_FP64 || prec == FCMP_FP32) && t >= 1) {
-      set_tuned_switch(cls, N, prec, t);
-      ++n;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    int cls = 0, prec = 0, t = 0, bucket = 0, tile = 0, th = 0, rth = 0;
+    long long N = 0;
+    char arch[128] = {0};
+    auto shape_ok = [&] {
+      return (cls == FCMP_HADAMARD || cls == FCMP_FOURIER) && N >= 2 && (N & (N - 1)) == 0 &&
+             (prec == FCMP_FP64 || prec == FCMP_FP32);
+    };
+    if (std::sscanf(line, "sched %127s %d %lld %d %d %d %d %d", arch, &cls, &N, &prec, &bucket,
+                    &tile, &th, &rth) == 8) {
+      if (shape_ok() && bucket >= 0 && bucket <= 4 && tile >= 0 && tile <= 8192 &&
+          (tile & (tile - 1)) == 0 && th >= 0 && th <= 256 && rth >= 0 && rth <= 256) {
+        set_tuned_sched(arch, cls, N, prec, bucket, Sched{tile, th, rth});
+        ++n;
+      }
+    } else if (std::sscanf(line, "%d %lld %d %d", &cls, &N, &prec, &t) == 4) {
+      if (shape_ok() && t >= 1) {
+        set_tuned_switch(cls, N, prec, t);
+        ++n;
+      }
     }
   }
   std::fclose(f);

@@ -238,11 +238,68 @@ const Tune& tune() {
   return t;
 }
 
-int pick_threads(int tile_n) {
+int pick_threads(int tile_n, int cap) {
   int t = tile_n / 8;
   if (t < 64) t = 64;
-  if (t > tune().threads) t = tune().threads;
+  const int c = cap > 0 ? cap : tune().threads;
+  if (t > c) t = c;
   return t;
+}
+
+namespace {
+std::mutex g_sched_mu;
+std::map<std::tuple<std::string, int, int64_t, int, int>, Sched> g_sched;
+}  // namespace
+
+int batch_bucket(int64_t n) {
+  if (n <= 1) return 0;
+  if (n <= 8) return 1;
+  if (n <= 32) return 2;
+  if (n <= 128) return 3;
+  return 4;
+}
+
+std::string device_arch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return std::string();
+  static std::mutex mu;
+  static std::map<int, std::string> names;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = names.find(dev);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop{};
+  std::string a;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    if (c != std::string::npos) a.resize(c);
+  }
+  names[dev] = a;
+  return a;
+}
+
+bool tuned_sched(int cls, int64_t N, int prec, int64_t n, Sched* s) {
+  {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    if (g_sched.empty()) return false;   // no device query while nothing is tuned
+  }
+  const std::string arch = device_arch();
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  auto it = g_sched.find(std::make_tuple(arch, cls, N, prec, batch_bucket(n)));
+  if (it == g_sched.end()) return false;
+  *s = it->second;
+  return true;
+}
+
+void set_tuned_sched(const std::string& arch, int cls, int64_t N, int prec, int bucket,
+                     const Sched& s) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  g_sched[std::make_tuple(arch, cls, N, prec, bucket)] = s;
+}
+
+bool erase_tuned_sched(const std::string& arch, int cls, int64_t N, int prec, int bucket) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  return g_sched.erase(std::make_tuple(arch, cls, N, prec, bucket)) > 0;
 }
 
 hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const EntDev& en,
@@ -291,7 +348,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
     p.inter_tw = 0;
     p.scale = out.scale;
     p.partial = out.partial; p.inst_part = isp;
-    p.nthreads = pick_threads(g.N);
+    p.nthreads = pick_threads(g.N, g.threads);
     p.role = 0;
     p.resid = out.resid ? 1 : 0;
     p.log_out_es = 0;
@@ -313,7 +370,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   a.scale = 1.0;
   a.partial = nullptr; a.excl = nullptr; a.excl_mode = 0;
   a.resid = 0;
-  a.nthreads = pick_threads(a.L * a.B);
+  a.nthreads = pick_threads(a.L * a.B, g.threads);
   a.role = 1;
   if (!in.pass2_only) {
     hipError_t e = (in.mode == IN_TAPS && taps_pass1_ok(a, vk))
@@ -335,7 +392,7 @@ hipError_t run_transform(int vk, int sign, const Geo& g, const TwDev& tw, const 
   b.inter_tw = 0;
   b.scale = out.scale;
   b.partial = out.partial; b.inst_part = isp;
-  b.nthreads = pick_threads(b.L * b.B);
+  b.nthreads = pick_threads(b.L * b.B, g.threads);
   b.role = 2;
   b.resid = out.resid ? 1 : 0;
   b.log_out_es = fft ? g.n2 : 0;

@@ -26,6 +26,7 @@ struct Geo {
   int ngroups2 = 1;          // pass-2 workgroups = N2 / B2
   bool same_out = true;      // pass-2 output groups coincide with pass-1 input groups
   int hmax = 0;              // largest span of a twiddled radix-16 stage (Fourier)
+  int threads = 0;           // most threads per transform workgroup (0: the default)
 };
 // Twiddle entries per precision: two-level table (lo 2^twS, hi N >> twS) for
 // the inter-pass twiddle, then the per-span stage table of the LDS core.
@@ -65,7 +66,23 @@ int plan_tile(int64_t n);
 int transform_partials(int vk, const Geo& g, bool store);
 int transform_partials_max(const Geo& g);
 int xrow_rows_per_group(const Geo& g);
-int pick_threads(int tile_n);                    // threads of a transform workgroup
+int pick_threads(int tile_n, int cap = 0);       // threads of a transform workgroup
+
+// Launch schedule of a plan: the transform tile, the most threads of a
+// transform workgroup and the threads of the fused residual's first pass
+// (0: the defaults).  No field changes a result: each only splits the same
+// per-element arithmetic, and the identification's total order, over
+// workgroups and threads differently.  Tuned schedules are kept per (device
+// architecture, class, N, precision, batch bucket).
+struct Sched {
+  int tile = 0, threads = 0, rthreads = 0;
+};
+int batch_bucket(int64_t n);                     // 0: 1, 1: <= 8, 2: <= 32, 3: <= 128, 4: more
+std::string device_arch();                       // of the current device ("" without one)
+bool tuned_sched(int cls, int64_t N, int prec, int64_t n, Sched* s);
+void set_tuned_sched(const std::string& arch, int cls, int64_t N, int prec, int bucket,
+                     const Sched& s);
+bool erase_tuned_sched(const std::string& arch, int cls, int64_t N, int prec, int bucket);
 
 struct HostTables {
   std::vector<int32_t> ent_k, perm, goff;   // entry order (grouped or Omega order)

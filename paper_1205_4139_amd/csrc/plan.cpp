@@ -41,6 +41,28 @@ RCParams rcorr_geometry(const fcmp_plan& P) {
 
 int rcorr_threads(const RCParams& q) { return std::min(256, std::max(64, q.B * q.L / 8)); }
 
+Sched plan_sched(const fcmp_plan& P) {
+  Sched s;
+  s.tile = P.g.B1 << P.g.n2;
+  s.threads = P.g.threads > 0 ? P.g.threads : tune().threads;
+  if (P.fused && !P.rreg) s.rthreads = P.rthreads > 0 ? P.rthreads : rcorr_threads(rcorr_geometry(P));
+  return s;
+}
+
+int plan_set_threads(fcmp_plan& P, int threads, int rthreads) {
+  if (threads != 0 && (threads < 64 || threads > 256 || (threads & (threads - 1))))
+    return set_error(FCMP_E_INVALID, "transform threads must be 64, 128 or 256");
+  if (rthreads != 0) {
+    if (!P.fused || P.rreg) return set_error(FCMP_E_INVALID, "no generic fused first pass");
+    const RCParams q = rcorr_geometry(P);
+    if (!rcorr_ok(P.pk, P.g.fourier, q, rthreads))
+      return set_error(FCMP_E_INVALID, "the fused first pass cannot run with that many threads");
+  }
+  P.g.threads = threads;
+  P.rthreads = rthreads;
+  return FCMP_OK;
+}
+
 int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_options* opt,
               int tile) {
   if (n < 1) return set_error(FCMP_E_INVALID, "n must be >= 1");
@@ -73,7 +95,12 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
   P.shape.omega = nullptr;
   P.opt = *opt;
   const bool F = P.shape.matrix_class == FCMP_FOURIER;
+  Sched sc;
+  P.sched_tuned = tile <= 0 && !tune().tile_fixed &&
+                  tuned_sched(big.matrix_class, big.N, opt->corr_precision, n, &sc);
+  if (P.sched_tuned && sc.tile > 0) tile = sc.tile;
   P.g = make_geo(F, (int)P.shape.N, tile > 0 ? tile : plan_tile(n));
+  if (P.sched_tuned) P.g.threads = sc.threads;
   P.wk = F ? V_C128 : V_F64;
   P.pk = opt->corr_precision == FCMP_FP32 ? (F ? V_C64 : V_F32) : P.wk;
   const int64_t N = P.shape.N, M = P.shape.M, K = P.shape.K;
@@ -93,6 +120,10 @@ int plan_init(fcmp_plan& P, int64_t n, const fcmp_problem* probs, const fcmp_opt
     q.cbase = (const int32_t*)&P;
     P.rreg = rcorr_reg_ok(P.pk, F, q);
     P.fused = P.rreg || rcorr_ok(P.pk, F, q, rcorr_threads(q));
+    // a tuned thread count is taken only where the fused pass runs with it
+    if (P.sched_tuned && sc.rthreads > 0 && P.fused && !P.rreg &&
+        rcorr_ok(P.pk, F, q, sc.rthreads))
+      P.rthreads = sc.rthreads;
   }
   P.sC = pad64(N / 32);
   P.sCs = pad64(((int64_t)1 << P.g.n1) + 1);
@@ -441,7 +472,8 @@ static int conv_corr(fcmp_plan& P, int t, int* npart, hipStream_t st, const int3
     q.status = P.status;
     q.cmask = P.cmask; q.cbase = P.cbase; q.inst_cmask = P.sC;
     if (P.rreg) HIP_TRY(launch_rcorr_reg(P.pk, F, q, n, st));
-    else HIP_TRY(launch_rcorr(P.pk, F, q, (1 << g.n1) / q.B, n, rcorr_threads(q), st));
+    else HIP_TRY(launch_rcorr(P.pk, F, q, (1 << g.n1) / q.B, n,
+                              P.rthreads > 0 ? P.rthreads : rcorr_threads(q), st));
     XDst d;
     d.partial = P.partial; d.excl = P.excl;
     d.scale = inv_sqrt_n;

@@ -21,6 +21,8 @@ struct fcmp_plan {
   double resid_ratio = 1.0;    // transform residual when M (t-1) > ratio * N log2 N
   bool fused = false;          // residual fused into the correlation's first pass
   bool rreg = false;           //   by the register-resident kernel (N2 = 256)
+  int rthreads = 0;            //   threads of the generic fused first pass (0: default)
+  bool sched_tuned = false;    // the launch schedule came from the tuned table
   int64_t sB = 0;              // bucket starts per buffer (N2 + 1, padded)
   int npart = 1;
   // shared
@@ -104,6 +106,11 @@ int plan_set_tap_order(fcmp_plan& P, const int32_t* lam, int ntaps, hipStream_t 
                        std::vector<int32_t>& ord, std::vector<int32_t>& bst);
 RCParams rcorr_geometry(const fcmp_plan& P);
 int rcorr_threads(const RCParams& q);
+// The launch schedule the plan uses (tile, transform threads, first-pass threads).
+Sched plan_sched(const fcmp_plan& P);
+// Sets the plan's thread counts (0: defaults); FCMP_E_INVALID when the fused
+// first pass cannot run with rthreads.
+int plan_set_threads(fcmp_plan& P, int threads, int rthreads);
 // Fills stats from host copies of the status records; FCMP_E_NUMERIC when any
 // instance broke down.
 int plan_stats(int64_t n, const Status* hs, double ms, fcmp_stats* stats,

@@ -211,3 +211,26 @@ def test_phase_times_flag_accepted(fc):
     assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == 0
     o = fc.make_options(flags=64)
     assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID
+
+
+def test_schedule_host_only(fc, tmp_path):
+    """Launch schedules: the defaults a plan shape uses, argument checks, and
+    cache lines of both kinds loading (no device: an entry recorded for
+    another device's architecture is never used)."""
+    g = fc.schedule_get("F", 1 << 16, "fp32", 256)
+    assert g == {"tile": 2048, "threads": 256, "rthreads": 0, "tuned": False}
+    g = fc.schedule_get("H", 1 << 18, "fp32", 8)
+    assert g["tile"] == 512 and g["rthreads"] in (64, 128, 256) and not g["tuned"]
+    for bad in ((3000, 0, 0), (512, 96, 0), (512, 0, 512), (16384, 0, 0)):
+        with pytest.raises(fc.FcmpError, match="tile must be"):
+            fc.schedule_set("F", 1 << 16, "fp32", 8, *bad)
+    nb = ctypes.c_size_t(0)
+    assert fc.lib.fcmp_schedule_query_workspace(fc.CLASS["F"], 1 << 16, 16384, fc.PREC["fp32"], 8,
+                                                ctypes.byref(nb)) == 0
+    assert nb.value > 8 * 16384 * 16
+    assert fc.lib.fcmp_schedule_query_workspace(fc.CLASS["F"], 1 << 16, 8, fc.PREC["fp32"], 8,
+                                                ctypes.byref(nb)) == fc.E_INVALID
+    p = tmp_path / "cache.txt"
+    p.write_text("sched gfx-none 1 65536 1 4 1024 128 0\n1 8388608 1 7\nbogus line\n")
+    fc.autotune_load(str(p))
+    assert not fc.schedule_get("F", 1 << 16, "fp32", 256)["tuned"]

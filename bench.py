@@ -358,6 +358,14 @@ def cfg0_leg(fc, device, count: int, reps: int):
     }
 
 
+def sched_record(r: dict) -> dict:
+    return {"tile": r["tile"], "transform_threads": r["threads"] or 256,
+            "first_pass_threads": r["rthreads"] or "default",
+            "ms_default": round(r["ms_default"], 4), "ms_tuned": round(r["ms_best"], 4),
+            "timed": "one conventional correlation (t = 16) + the h_0 / kernel-vector share "
+                     "of a 256-iteration solve, over the plan's batch"}
+
+
 def cfg2_leg(fc, device):
     """Partial Hadamard N = 2^20, M = 2^17, K = 1024, +-U(1,2) values,
     noiseless (instance 0, seed 3000), FP32 correlation and FP64 least
@@ -374,6 +382,7 @@ def cfg2_leg(fc, device):
     NN, MM, KK = inst.N, inst.M, inst.K
     out = {"workload": "partial Hadamard N=2^20 M=2^17 K=1024, +-U(1,2) values, noiseless, "
                        "FP32 correlation + FP64 LS, single instance"}
+    out["schedule"] = sched_record(fc.schedule_tune("H", NN, MM, "fp32", batch=1, device=device))
     fc.solve("H", NN, MM, KK, inst.omega, y, precision="fp32")   # warm-up
     for alg, methods in (("omp", ("conventional", "adaptive")), ("sp", ("conventional", "fast")),
                          ("cosamp", ("conventional", "fast"))):
@@ -655,6 +664,11 @@ def main():
     B = args.batch
     insts, ys = make_inputs(B, dev)
     print(f"[bench] inputs ready: B={B} N={N} M={M} K={K}", file=sys.stderr, flush=True)
+    # launch schedule (transform tile, thread counts) for this plan shape:
+    # timed candidates, the fastest kept; results do not depend on it
+    schedules = {"workload": sched_record(fc.schedule_tune("F", N, M, "fp32", batch=B,
+                                                           device=dev))}
+    print(f"[bench] schedule: {schedules['workload']}", file=sys.stderr, flush=True)
     plan = fc.Plan("F", N, M, K, [i.omega for i in insts], precision="fp32",
                    method="conventional", device=dev)
 
@@ -809,6 +823,11 @@ def main():
         "serving_sweep": serve_low,
         "accuracy": accuracy,
         "configs": {"hadamard_n1024_single": cfg0, "hadamard_n1m": cfg2},
+        "schedules": {**schedules,
+                      "hadamard_n1m": cfg2.get("schedule") if cfg2 else None,
+                      "uneven_batch": "persistent one-workgroup-per-problem kernel (512 threads: "
+                                      "its workgroup size fixes the order of its sums, so it is "
+                                      "not a schedule field)"},
         "per_t": per_t,
         "roofline": {
             "kernel": "conventional correlation launch pair, B instances: the FP64 residual "

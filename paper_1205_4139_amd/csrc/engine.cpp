@@ -69,9 +69,12 @@ Geo make_geo(bool fourier, int N, int tile_req) {
   g.N = N;
   g.fourier = fourier;
   g.logN = ilog2(N);
-  g.twS = g.logN / 2;
   g.n2 = g.logN / 2;
+  // N = 2^18: columns of 256 rows, so the residual-fused first pass runs
+  // register-resident, and rows of 1024 for the second pass
+  if (g.logN == 18) g.n2 = 8;
   g.n1 = g.logN - g.n2;
+  g.twS = g.n2;
   const int tile = tile_req > 0 ? tile_req : tune().tile;
   g.B1 = std::min(1 << g.n1, std::max(1, tile >> g.n2));
   g.B2 = std::min(1 << g.n2, std::max(1, tile >> g.n1));

@@ -123,7 +123,7 @@ struct RCParams {
 bool rcorr_ok(int pk, bool fft, const RCParams& p, int nthreads);
 hipError_t launch_rcorr(int pk, bool fft, const RCParams& p, int groups, int ninst, int nthreads,
                         hipStream_t st);
-// The register-resident variant for N2 = 256 rows per column (N = 2^16, 2^17),
+// The register-resident variant for N2 = 256 rows per column (N = 2^16 .. 2^18),
 // 16 columns per workgroup; needs cmask and cbase.
 bool rcorr_reg_ok(int pk, bool fft, const RCParams& p);
 hipError_t launch_rcorr_reg(int pk, bool fft, const RCParams& p, int ninst, hipStream_t st);

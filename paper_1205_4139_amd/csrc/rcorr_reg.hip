@@ -1,6 +1,6 @@
 // Residual (Algorithm 1.1, step 7) fused with the first pass of the next
 // correlation (step 2), register-resident, for columns of N2 = 256 rows
-// (N = 2^16 and 2^17).
+// (N = 2^16, 2^17 and 2^18).
 //
 // The algebra is that of rcorr_kernel: with bucket l of a tap lam (lam mod N2
 // for Fourier, lam >> log2 N1 for Hadamard),
@@ -256,7 +256,7 @@ rcorr_reg_kernel(RCParams p) {
 }
 
 bool rcorr_reg_ok(int pk, bool fft, const RCParams& p) {
-  return p.L == RR_L && (p.logN1 == 8 || p.logN1 == 9) && p.cmask && p.cbase &&
+  return p.L == RR_L && p.logN1 >= 8 && p.logN1 <= 10 && p.cmask && p.cbase &&
          (fft ? (pk == V_C64 || pk == V_C128) : (pk == V_F32 || pk == V_F64));
 }
 

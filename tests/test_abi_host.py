@@ -219,8 +219,9 @@ def test_schedule_host_only(fc, tmp_path):
     another device's architecture is never used)."""
     g = fc.schedule_get("F", 1 << 16, "fp32", 256)
     assert g == {"tile": 2048, "threads": 256, "rthreads": 0, "tuned": False}
-    g = fc.schedule_get("H", 1 << 18, "fp32", 8)
-    assert g["tile"] == 512 and g["rthreads"] in (64, 128, 256) and not g["tuned"]
+    g = fc.schedule_get("H", 1 << 20, "fp32", 8)
+    assert g["tile"] == 1024 and g["rthreads"] in (64, 128, 256) and not g["tuned"]
+    assert fc.schedule_get("H", 1 << 18, "fp32", 8)["rthreads"] == 0   # register-resident pass
     for bad in ((3000, 0, 0), (512, 96, 0), (512, 0, 512), (16384, 0, 0)):
         with pytest.raises(fc.FcmpError, match="tile must be"):
             fc.schedule_set("F", 1 << 16, "fp32", 8, *bad)

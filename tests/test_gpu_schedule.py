@@ -39,8 +39,9 @@ def _solve(fc, cls, N, M, K, insts, ys):
 CASES = [
     # (class, N, M, K, batch, schedules (tile, threads, rthreads))
     ("F", 1 << 16, 16384, 64, 8, [(512, 64, 0), (4096, 128, 0), (8192, 256, 0)]),
-    ("H", 1 << 18, 32768, 48, 4, [(256, 128, 64), (2048, 64, 256), (8192, 256, 128)]),
-    ("F", 1 << 18, 40000, 40, 1, [(1024, 64, 128), (4096, 256, 64)]),
+    ("H", 1 << 20, 32768, 48, 4, [(256, 128, 64), (2048, 64, 256), (8192, 256, 128)]),
+    ("F", 1 << 19, 40000, 40, 1, [(1024, 64, 128), (4096, 256, 64)]),
+    ("H", 1 << 18, 30000, 40, 2, [(512, 64, 0), (8192, 128, 0)]),
     ("F", 1 << 12, 1000, 30, 3, [(256, 64, 0), (2048, 128, 0)]),
 ]
 

@@ -31,13 +31,25 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
   __shared__ int32_t sl[F_TCH];
   __shared__ Wd sx[F_TCH];
   __shared__ Sel red[16];
-  const int inst = blockIdx.y;
+  // Workgroups are dispatched to the eight XCDs round-robin by linear id.
+  // With xcd_map, the one-dimensional grid is read so that XCD x runs the
+  // instances x, x + 8, ... one after another: an instance's kernel vector
+  // then stays in one XCD's L2 while its workgroups gather from it.
+  int inst, grp;
+  if (p.xcd_map) {
+    const int L = blockIdx.x, k = L >> 3;
+    inst = (L & 7) + 8 * (k / p.groups);
+    grp = k % p.groups;
+  } else {
+    inst = blockIdx.y;
+    grp = blockIdx.x;
+  }
   if (p.status && p.status[inst].done) return;
   const int tid = threadIdx.x;
   const uint32_t mask = (uint32_t)p.N - 1u;
   const bool half = p.c_half != 0;
   const uint32_t half_n = (uint32_t)p.N >> 1;
-  const int64_t jb = (int64_t)blockIdx.x * (F_THREADS * JPT) + tid;
+  const int64_t jb = (int64_t)grp * (F_THREADS * JPT) + tid;
   const Wd* h0 = (const Wd*)p.h0 + (int64_t)inst * p.inst_h0;
   const VC* c = (const VC*)p.c + (int64_t)inst * p.inst_c;
   const int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
@@ -114,43 +126,48 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
   }
   if (p.partial) {
     const Sel r = block_sel_reduce(bkey, bidx, bkey2, red);
-    if (tid == 0) p.partial[(int64_t)inst * p.inst_part + blockIdx.x] = r;
+    if (tid == 0) p.partial[(int64_t)inst * p.inst_part + grp] = r;
   }
 }
 
-static int jpt_for(int N) {
-  // enough workgroups to cover the chip for one instance, wider tiles beyond
-  if (N <= (1 << 17)) return 1;
-  if (N <= (1 << 19)) return 2;
-  return 4;
+// Outputs per thread: enough workgroups to cover the chip (about 16 per CU)
+// for the whole launch, wider tiles (fewer workgroups, less per-workgroup
+// staging) beyond.  Each output's sum runs over the taps in order whatever
+// the width, so the width never changes a result.
+static int jpt_for(int N, int ninst) {
+  int jpt = N <= (1 << 17) ? 1 : (N <= (1 << 19) ? 2 : 4);
+  while (jpt < 8 && (int64_t)ninst * (N / (F_THREADS * jpt * 2)) >= 4096) jpt *= 2;
+  return jpt;
 }
 
 int fastcorr_groups(int N) {
-  const int jpt = jpt_for(N);
+  const int jpt = jpt_for(N, 1);
   return (N + F_THREADS * jpt - 1) / (F_THREADS * jpt);
 }
 
 template <class VC>
-static hipError_t launch_v(const FParams& p, int ninst, hipStream_t st) {
-  const int jpt = jpt_for(p.N);
-  const int groups = fastcorr_groups(p.N);
-  dim3 grid(groups, ninst);
+static hipError_t launch_v(FParams p, int ninst, int jpt, hipStream_t st) {
+  p.groups = (p.N + F_THREADS * jpt - 1) / (F_THREADS * jpt);
+  p.xcd_map = ninst >= 8 && ninst % 8 == 0 && (int64_t)p.groups * ninst < (int64_t(1) << 31);
+  const dim3 grid = p.xcd_map ? dim3(p.groups * ninst) : dim3(p.groups, ninst);
   switch (jpt) {
     case 1: hipLaunchKernelGGL((fastcorr_kernel<VC, 1>), grid, dim3(F_THREADS), 0, st, p); break;
     case 2: hipLaunchKernelGGL((fastcorr_kernel<VC, 2>), grid, dim3(F_THREADS), 0, st, p); break;
-    default: hipLaunchKernelGGL((fastcorr_kernel<VC, 4>), grid, dim3(F_THREADS), 0, st, p); break;
+    case 4: hipLaunchKernelGGL((fastcorr_kernel<VC, 4>), grid, dim3(F_THREADS), 0, st, p); break;
+    default: hipLaunchKernelGGL((fastcorr_kernel<VC, 8>), grid, dim3(F_THREADS), 0, st, p); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_fastcorr(const FParams& p, int ninst, int* groups_out, hipStream_t st) {
-  if (groups_out) *groups_out = fastcorr_groups(p.N);
-  if (p.c_int16) return launch_v<int16_t>(p, ninst, st);
+  const int jpt = jpt_for(p.N, ninst);
+  if (groups_out) *groups_out = (p.N + F_THREADS * jpt - 1) / (F_THREADS * jpt);
+  if (p.c_int16) return launch_v<int16_t>(p, ninst, jpt, st);
   switch (p.c_kind) {
-    case V_F32: return launch_v<float>(p, ninst, st);
-    case V_F64: return launch_v<double>(p, ninst, st);
-    case V_C64: return launch_v<float2>(p, ninst, st);
-    case V_C128: return launch_v<double2>(p, ninst, st);
+    case V_F32: return launch_v<float>(p, ninst, jpt, st);
+    case V_F64: return launch_v<double>(p, ninst, jpt, st);
+    case V_C64: return launch_v<float2>(p, ninst, jpt, st);
+    case V_C128: return launch_v<double2>(p, ninst, jpt, st);
   }
   return hipErrorInvalidValue;
 }

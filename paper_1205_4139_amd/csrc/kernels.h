@@ -172,6 +172,9 @@ struct FParams {
   const uint32_t* excl;
   const Status* status;
   int64_t inst_h0, inst_c, inst_lam, inst_x, inst_h, inst_part, inst_excl;
+  // set by the launcher: workgroups per instance, and whether the grid is
+  // one-dimensional with every workgroup of instance i on XCD i mod 8
+  int groups, xcd_map;
 };
 hipError_t launch_fastcorr(const FParams& p, int ninst, int* groups_out, hipStream_t st);
 int fastcorr_groups(int N);

@@ -446,6 +446,29 @@ def per_t_leg(fc, device):
     return out
 
 
+def pairing_leg(fc, device):
+    """The conjugate-symmetric pairing (FCMP_FLAG_CONJ_PAIR) against the
+    unpaired fast correlation (full and half kernel-vector gathers) and the
+    conventional one, per iteration t, for partial Fourier N = 8192, M = 2048,
+    complex64 kernel vector, at batch 1 and 256.  The paired kernel makes
+    (N/2)(t-1) complex multiplications per correlation instead of N(t-1)."""
+    NN, MM, ts = 8192, 2048, (2, 8, 32, 128, 256)
+    out = {"workload": "partial Fourier N=8192 M=2048, complex64 kernel vector, FP64 "
+                       "accumulation; ms per correlation launch sequence over the batch"}
+    for b in (1, 256):
+        full, conv = fc.corr_curve("F", NN, MM, ts, precision="fp32", batch=b, device=device)
+        half, _ = fc.corr_curve("F", NN, MM, ts, precision="fp32", batch=b, device=device,
+                                flags=fc.FLAG_HALF_KERNEL)
+        pair, _ = fc.corr_curve("F", NN, MM, ts, precision="fp32", batch=b, device=device,
+                                flags=fc.FLAG_CONJ_PAIR)
+        out[f"batch{b}"] = [{"t": t, "fast_full_ms": round(f, 4), "fast_half_ms": round(h, 4),
+                             "fast_paired_ms": round(q, 4), "conv_ms": round(c, 4),
+                             "paired_complex_mults": b * (NN // 2) * (t - 1),
+                             "unpaired_complex_mults": b * NN * (t - 1)}
+                            for t, f, h, q, c in zip(ts, full, half, pair, conv)]
+    return out
+
+
 def serve_bound(count: int = 4000):
     """HBM-bound ceiling of the serving mix: mean algorithmic bytes per
     request of the slot path over `count` draws of the stream's (class, N, M,
@@ -605,7 +628,7 @@ def main():
                     help="N = 1024 Hadamard single-instance leg: instances (0: skip)")
     ap.add_argument("--no-cfg2", action="store_true", help="skip the N = 2^20 Hadamard leg")
     ap.add_argument("--no-per-t", action="store_true", help="skip the per-iteration cost curves")
-    ap.add_argument("--only", choices=("cfg0", "cfg2", "batch", "per_t"),
+    ap.add_argument("--only", choices=("cfg0", "cfg2", "batch", "per_t", "pairing"),
                     help="run that leg alone and print its record (for profiling); no metric line")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
@@ -657,6 +680,8 @@ def main():
             rec = cfg2_leg(fc, dev)
         elif args.only == "batch":
             rec = batch_leg(fc, dev, args.batch_count, max(args.steps, 1), 8)
+        elif args.only == "pairing":
+            rec = pairing_leg(fc, dev)
         else:
             rec = per_t_leg(fc, dev)
         print(json.dumps({"leg": args.only, "record": rec}))
@@ -788,6 +813,9 @@ def main():
     if not args.no_per_t:
         per_t = per_t_leg(fc, dev)
         print(f"[bench] per-t: {per_t}", file=sys.stderr, flush=True)
+        per_t["conj_pairing_fourier_n8192"] = pairing_leg(fc, dev)
+        print(f"[bench] pairing: {per_t['conj_pairing_fourier_n8192']}", file=sys.stderr,
+              flush=True)
     cpu_rec = orc = None
     if not args.no_cpu:
         cpu_rec, orc = cpu_baseline(insts[0], args.cpu_iters, args.cpu_single_iters)

@@ -133,6 +133,16 @@ typedef struct {
  * the solve's stream (a small overhead per launch).  Ignored under graph
  * capture and by the persistent batch kernel. */
 #define FCMP_FLAG_PHASE_TIMES 16u
+/* Fourier plans with N <= 8192, fast correlation: the conjugate-symmetric
+ * pairing of Sec. III-B (complexity of the proposed OMP, partial Fourier).
+ * Because c(N - m) = conj(c(m)), the four real products of x c(m) give both
+ * x c(m), added at h(lambda + m), and x conj(c(m)), added at h(lambda - m):
+ * (N/2)(t - 1) complex multiplications per correlation.  One workgroup per
+ * instance holds h in LDS and takes the taps in order.  Like
+ * FCMP_FLAG_HALF_KERNEL it reads c only up to N/2, so results agree with the
+ * full gathers to rounding, not bit for bit.  FCMP_E_INVALID for the Hadamard
+ * class or N > 8192; ignored by the persistent batch kernel. */
+#define FCMP_FLAG_CONJ_PAIR 32u
 
 /* Per-solve statistics. */
 typedef struct {
@@ -367,15 +377,17 @@ int fcmp_autotune(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_preci
  * written to fast_ms[i] and conv_ms[i] (ms per launch sequence over the whole
  * batch, mean of a few repetitions).  This is the per-iteration cost curve
  * whose crossing is the adaptive strategy's switch (Sec. IV; Table I gives
- * the flop-count version).  The workspace size comes from
+ * the flop-count version).  flags: FCMP_FLAG_HALF_KERNEL, FCMP_FLAG_CONJ_PAIR
+ * or FCMP_FLAG_FLOAT_KERNEL select the fast correlation's variant (others:
+ * FCMP_E_INVALID).  The workspace size comes from
  * fcmp_corr_curve_query_workspace with tmax = max ts (host-only).  The call
  * synchronises the stream. */
 int fcmp_corr_curve_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
                                     int32_t corr_precision, int32_t batch, int32_t tmax,
                                     size_t* bytes);
 int fcmp_corr_curve(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
-                    int32_t batch, const int32_t* ts, int32_t nt, void* ws_dev, size_t ws_bytes,
-                    float* fast_ms, float* conv_ms, void* hip_stream);
+                    int32_t batch, uint32_t flags, const int32_t* ts, int32_t nt, void* ws_dev,
+                    size_t ws_bytes, float* fast_ms, float* conv_ms, void* hip_stream);
 /* Loads every valid entry of a cache file (switch iterations and launch
  * schedules) into the tables (host-only); FCMP_E_NOTFOUND when the file is
  * missing or holds no valid entry. */

@@ -68,6 +68,7 @@ NPHASE = 8
 PHASES = ["kernel", "h0", "corr", "fast", "resid", "ls", "other", "select"]
 FLAG_RECOMPUTE_KERNEL = 1
 FLAG_PHASE_TIMES = 16
+FLAG_CONJ_PAIR = 32
 
 
 class ServerConfig(ctypes.Structure):
@@ -134,7 +135,7 @@ def _load():
                                ctypes.POINTER(i32)], ctypes.c_int),
         "fcmp_corr_curve_query_workspace": ([i32, i64, i64, i32, i32, i32, ctypes.POINTER(sz)],
                                             ctypes.c_int),
-        "fcmp_corr_curve": ([i32, i64, i64, i32, i32, ctypes.POINTER(i32), i32, vp, sz,
+        "fcmp_corr_curve": ([i32, i64, i64, i32, i32, ctypes.c_uint32, ctypes.POINTER(i32), i32, vp, sz,
                              ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), vp],
                             ctypes.c_int),
         "fcmp_adaptive_switch": ([i32, i64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)],
@@ -601,9 +602,10 @@ def autotune(cls, N, M, precision="fp32", batch=8, cache_path=None, device="cuda
     return t.value
 
 
-def corr_curve(cls, N, M, ts, precision="fp32", batch=1, device="cuda"):
+def corr_curve(cls, N, M, ts, precision="fp32", batch=1, device="cuda", flags=0):
     """Per-iteration device time (ms per launch sequence over the batch) of
-    the fast and the conventional correlation at each iteration t in ts."""
+    the fast and the conventional correlation at each iteration t in ts
+    (flags: the fast correlation's kernel-vector variant)."""
     ts = [int(t) for t in ts]
     nb = ctypes.c_size_t(0)
     _check(lib.fcmp_corr_curve_query_workspace(CLASS[cls], int(N), int(M), PREC[precision],
@@ -612,7 +614,8 @@ def corr_curve(cls, N, M, ts, precision="fp32", batch=1, device="cuda"):
     ta = (ctypes.c_int32 * len(ts))(*ts)
     fa = (ctypes.c_float * len(ts))()
     ca = (ctypes.c_float * len(ts))()
-    _check(lib.fcmp_corr_curve(CLASS[cls], int(N), int(M), PREC[precision], int(batch), ta,
+    _check(lib.fcmp_corr_curve(CLASS[cls], int(N), int(M), PREC[precision], int(batch),
+                               int(flags), ta,
                                len(ts), _ptr(ws), ws.numel(), fa, ca, _stream()))
     return list(fa), list(ca)
 

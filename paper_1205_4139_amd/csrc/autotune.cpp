@@ -92,7 +92,8 @@ struct CurveBench {
 };
 
 int curve_setup(CurveBench& C, int32_t cls, int64_t N, int64_t M, int32_t prec, int32_t batch,
-                int32_t tmax, void* ws_dev, size_t ws_bytes, hipStream_t st, int tile = 0) {
+                int32_t tmax, void* ws_dev, size_t ws_bytes, hipStream_t st, int tile = 0,
+                uint32_t flags = 0) {
   fcmp_options opt;
   int rc = tune_shape(cls, N, M, batch, tmax, C.om, C.probs, opt, prec);
   if (rc) return rc;
@@ -119,6 +120,7 @@ int curve_setup(CurveBench& C, int32_t cls, int64_t N, int64_t M, int32_t prec, 
   HIP_TRY(launch_fill_u32((uint32_t*)P.h0, 0u, (int64_t)(batch * P.sN * wb / 4), st));
   HIP_TRY(launch_init_status(P.status, P.y_ent, (int)M, F, P.sM, batch, st));
   for (hipEvent_t& ev : C.e) HIP_TRY(hipEventCreate(&ev));
+  P.cur_flags = flags;   // kernel-vector variants of the fast correlation
   // warm up both paths (the host copies of x must land before the vector dies)
   int npart = 0;
   if ((rc = plan_set_tap_order(P, C.lam.data(), 1, st, C.hord, C.hbst)) ||
@@ -406,9 +408,13 @@ int fcmp_corr_curve_query_workspace(int32_t matrix_class, int64_t N, int64_t M,
 }
 
 int fcmp_corr_curve(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_precision,
-                    int32_t batch, const int32_t* ts, int32_t nt, void* ws_dev, size_t ws_bytes,
-                    float* fast_ms, float* conv_ms, void* hip_stream) {
+                    int32_t batch, uint32_t flags, const int32_t* ts, int32_t nt, void* ws_dev,
+                    size_t ws_bytes, float* fast_ms, float* conv_ms, void* hip_stream) {
   if (!ts || !fast_ms || !conv_ms || nt < 1) return set_error(FCMP_E_INVALID, "bad arrays");
+  if (flags & ~(FCMP_FLAG_HALF_KERNEL | FCMP_FLAG_CONJ_PAIR | FCMP_FLAG_FLOAT_KERNEL))
+    return set_error(FCMP_E_INVALID, "the curve takes only the kernel-vector flags");
+  if ((flags & FCMP_FLAG_CONJ_PAIR) && (matrix_class != FCMP_FOURIER || N > 8192))
+    return set_error(FCMP_E_INVALID, "FCMP_FLAG_CONJ_PAIR needs the Fourier class and N <= 8192");
   int tmax = 2;
   for (int i = 0; i < nt; ++i) {
     if (ts[i] < 2) return set_error(FCMP_E_INVALID, "every t must be >= 2");
@@ -417,7 +423,7 @@ int fcmp_corr_curve(int32_t matrix_class, int64_t N, int64_t M, int32_t corr_pre
   if (tmax > M - 1) return set_error(FCMP_E_INVALID, "t must be <= M - 1");
   CurveBench C;
   int rc = curve_setup(C, matrix_class, N, M, corr_precision, batch, tmax, ws_dev, ws_bytes,
-                       (hipStream_t)hip_stream);
+                       (hipStream_t)hip_stream, 0, flags);
   if (rc) return rc;
   for (int i = 0; i < nt; ++i)
     if ((rc = curve_point(C, ts[i], &fast_ms[i], &conv_ms[i]))) return rc;

@@ -443,8 +443,10 @@ int validate_options(const fcmp_problem* p, const fcmp_options* o) {
   if (!(o->res_tol >= 0.0 && o->res_tol < 1.0))
     return set_error(FCMP_E_INVALID, "res_tol must be in [0, 1)");
   if (o->flags & ~(FCMP_FLAG_RECOMPUTE_KERNEL | FCMP_FLAG_NO_PERSISTENT | FCMP_FLAG_FLOAT_KERNEL |
-                   FCMP_FLAG_HALF_KERNEL | FCMP_FLAG_PHASE_TIMES))
+                   FCMP_FLAG_HALF_KERNEL | FCMP_FLAG_PHASE_TIMES | FCMP_FLAG_CONJ_PAIR))
     return set_error(FCMP_E_INVALID, "unknown flags");
+  if ((o->flags & FCMP_FLAG_CONJ_PAIR) && (p->matrix_class != FCMP_FOURIER || p->N > 8192))
+    return set_error(FCMP_E_INVALID, "FCMP_FLAG_CONJ_PAIR needs the Fourier class and N <= 8192");
   if (o->algorithm == FCMP_OMP && p->K > 4096)
     return set_error(FCMP_E_INVALID, "OMP supports K <= 4096");
   if (o->algorithm == FCMP_SP && 2 * p->K > p->M)

@@ -130,6 +130,112 @@ __global__ void __launch_bounds__(F_THREADS) fastcorr_kernel(FParams p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// The conjugate-symmetric pairing of Sec. III-B (complexity, partial Fourier):
+// c(N - m) = conj(c(m)), so for a tap (lam, x) the four real products of
+// x c(m) give both x c(m), added at h(lam + m), and x conj(c(m)) = x c(N - m),
+// added at h(lam - m): (N/2) complex multiplications per tap instead of N.
+// The two outputs of a product are mirrors about the tap's own lam, so one
+// workgroup holds the whole h of its instance in LDS (N <= 8192 complex FP64)
+// and takes the taps in order: within a tap the outputs lam + m (m <= N/2)
+// and lam - m (0 < m < N/2) are all distinct, so each is updated by exactly
+// one thread, and a barrier separates taps.  Each thread keeps the kernel
+// vector values of its m in registers for the whole correlation.
+constexpr int FP_THREADS = 512;
+constexpr int FP_TCH = 256;     // taps staged per chunk
+constexpr int FP_NMAX = 8192;
+constexpr int FP_MPT = (FP_NMAX / 2 + FP_THREADS) / FP_THREADS;   // m values per thread
+
+template <class VC>
+__global__ void __launch_bounds__(FP_THREADS) fastpair_kernel(FParams p) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ Sel red[16];
+  const int inst = blockIdx.x;
+  if (p.status && p.status[inst].done) return;
+  const int tid = threadIdx.x;
+  const int N = p.N, half = p.N >> 1;
+  const uint32_t mask = (uint32_t)p.N - 1u;
+  double2* hs = (double2*)smem_raw;
+  int32_t* sl = (int32_t*)(hs + N);
+  double2* sx = (double2*)(sl + FP_TCH);
+  const double2* h0 = (const double2*)p.h0 + (int64_t)inst * p.inst_h0;
+  const VC* c = (const VC*)p.c + (int64_t)inst * p.inst_c;
+  const int32_t* lam = p.lam + (int64_t)inst * p.inst_lam;
+  const double2* xg = (const double2*)p.x + (int64_t)inst * p.inst_x;
+  for (int j = tid; j < N; j += FP_THREADS) hs[j] = h0[j];
+  double2 cm[FP_MPT];
+#pragma unroll
+  for (int q = 0; q < FP_MPT; ++q) {
+    const int m = tid + q * FP_THREADS;
+    cm[q] = m <= half ? cwiden2<VC>(c[m]) : make_double2(0.0, 0.0);
+  }
+  for (int base = 0; base < p.ntaps; base += FP_TCH) {
+    const int n = min(FP_TCH, p.ntaps - base);
+    __syncthreads();   // h loaded / the previous chunk's last tap is done
+    for (int e = tid; e < n; e += FP_THREADS) {
+      sl[e] = lam[base + e];
+      sx[e] = xg[base + e];
+    }
+    __syncthreads();
+    for (int tau = 0; tau < n; ++tau) {
+      const uint32_t l = (uint32_t)sl[tau];
+      const double2 xv = sx[tau];
+#pragma unroll
+      for (int q = 0; q < FP_MPT; ++q) {
+        const int m = tid + q * FP_THREADS;
+        if (m <= half) {
+          const double a = xv.x * cm[q].x, b = xv.y * cm[q].y;
+          const double e = xv.x * cm[q].y, f = xv.y * cm[q].x;
+          const uint32_t j1 = (l + (uint32_t)m) & mask;
+          hs[j1].x -= a - b;   // x c(m)
+          hs[j1].y -= e + f;
+          if (m != 0 && m != half) {
+            const uint32_t j2 = (l - (uint32_t)m) & mask;
+            hs[j2].x -= a + b;   // x conj(c(m))
+            hs[j2].y -= f - e;
+          }
+        }
+      }
+      __syncthreads();   // the next tap updates the same outputs
+    }
+  }
+  __syncthreads();
+  double bkey = -1.0, bkey2 = -1.0;
+  int64_t bidx = -1;
+  const uint32_t* excl = p.excl ? p.excl + (int64_t)inst * p.inst_excl : nullptr;
+  double2* hout = p.h ? (double2*)p.h + (int64_t)inst * p.inst_h : nullptr;
+  for (int j = tid; j < N; j += FP_THREADS) {
+    const double2 v = hs[j];
+    if (hout) hout[j] = v;
+    if (p.partial && (!excl || !bit_is_set(excl, j))) sel_add(vmag2(v), (int64_t)j, bkey, bidx, bkey2);
+  }
+  if (p.partial) {
+    const Sel r = block_sel_reduce(bkey, bidx, bkey2, red);
+    if (tid == 0) p.partial[(int64_t)inst * p.inst_part] = r;
+  }
+}
+
+bool fastpair_ok(const FParams& p) {
+  return p.fourier && p.N >= 2 && p.N <= FP_NMAX && (p.c_kind == V_C64 || p.c_kind == V_C128);
+}
+
+hipError_t launch_fastpair(const FParams& p, int ninst, int* groups_out, hipStream_t st) {
+  if (!fastpair_ok(p)) return hipErrorInvalidValue;
+  if (groups_out) *groups_out = 1;
+  const size_t lds = (size_t)p.N * 16 + (size_t)FP_TCH * 20;
+  if (p.c_kind == V_C64) {
+    hipError_t e = raise_lds_limit((const void*)fastpair_kernel<float2>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fastpair_kernel<float2>, dim3(ninst), dim3(FP_THREADS), lds, st, p);
+  } else {
+    hipError_t e = raise_lds_limit((const void*)fastpair_kernel<double2>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fastpair_kernel<double2>, dim3(ninst), dim3(FP_THREADS), lds, st, p);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Outputs per thread: enough workgroups to cover the chip (about 16 per CU)
 // for the whole launch, wider tiles (fewer workgroups, less per-workgroup
 // staging) beyond.  Each output's sum runs over the taps in order whatever

@@ -177,6 +177,10 @@ struct FParams {
   int groups, xcd_map;
 };
 hipError_t launch_fastcorr(const FParams& p, int ninst, int* groups_out, hipStream_t st);
+// The conjugate-symmetric pairing (Fourier, N <= 8192, h0 and x FP64): one
+// workgroup per instance, h in LDS, one identification partial per instance.
+bool fastpair_ok(const FParams& p);
+hipError_t launch_fastpair(const FParams& p, int ninst, int* groups_out, hipStream_t st);
 int fastcorr_groups(int N);
 
 // ------------------------------------------------------------------ least squares

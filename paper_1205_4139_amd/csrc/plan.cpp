@@ -431,6 +431,11 @@ int plan_fast_corr(fcmp_plan& P, int t, int* npart, hipStream_t st) {
   fp.h = nullptr; fp.partial = P.partial; fp.excl = P.excl; fp.status = P.status;
   fp.inst_h0 = P.sN; fp.inst_c = P.sN; fp.inst_lam = P.sK; fp.inst_x = P.sK;
   fp.inst_h = 0; fp.inst_part = P.sP; fp.inst_excl = P.sE;
+  if (P.cur_flags & FCMP_FLAG_CONJ_PAIR) {
+    fp.c_half = 0;
+    HIP_TRY(launch_fastpair(fp, (int)P.n, npart, st));
+    return FCMP_OK;
+  }
   HIP_TRY(launch_fastcorr(fp, (int)P.n, npart, st));
   return FCMP_OK;
 }

@@ -77,7 +77,8 @@ int correlate_set(const fcmp_plan& P, const Inst& I, bool fast, const int32_t* S
     fp.h0 = I.h0; fp.c = I.cp; fp.lam = S; fp.x = a; fp.ntaps = s;
     fp.h = P.hbuf; fp.partial = nullptr; fp.excl = nullptr; fp.status = nullptr;
     int groups = 0;
-    HIP_TRY(launch_fastcorr(fp, 1, &groups, st));
+    if (P.cur_flags & FCMP_FLAG_CONJ_PAIR) HIP_TRY(launch_fastpair(fp, 1, &groups, st));
+    else HIP_TRY(launch_fastcorr(fp, 1, &groups, st));
     *hkind = P.wk;
     return FCMP_OK;
   }

@@ -110,9 +110,17 @@ def test_options_validation(fc):
         _q(fc, precision=5)
     p, om = fc.make_problem("H", 1024, 256, 16, np.arange(256) * 4)
     o = fc.make_options()
-    o.flags = 32   # no such flag
+    o.flags = 64   # no such flag
     n = ctypes.c_size_t(0)
     assert fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID
+    # the conjugate-symmetric pairing: Fourier and N <= 8192 only
+    o.flags = fc.FLAG_CONJ_PAIR
+    with pytest.raises(fc.FcmpError, match="CONJ_PAIR"):
+        fc._check(fc.lib.fcmp_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(n)))
+    pf, omf = fc.make_problem("F", 8192, 2048, 16, np.arange(2048) * 4)
+    assert fc.lib.fcmp_query_workspace(ctypes.byref(pf), ctypes.byref(o), ctypes.byref(n)) == 0
+    pg, omg = fc.make_problem("F", 16384, 2048, 16, np.arange(2048) * 8)
+    assert fc.lib.fcmp_query_workspace(ctypes.byref(pg), ctypes.byref(o), ctypes.byref(n)) == fc.E_INVALID
 
 
 def test_server_footprint_host_only(fc):

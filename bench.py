@@ -634,7 +634,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
-    ap.add_argument("--serve-sweep", type=str, default="100,200,400,800,1600",
+    ap.add_argument("--serve-sweep", type=str, default="100,200,300,400,600,800",
                     help="offered rates (req/s) of the serving sweep, '' to skip")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="seconds of arrivals per sweep rate")

@@ -114,3 +114,40 @@ def test_fixed_omega_stream_reuses_tables(fc):
         sup, x = _alone(fc, i, y)
         assert np.array_equal(g["support"], sup)
         assert np.array_equal(g["x"], x)
+
+
+def test_slot_capacities_and_group_cycling(fc):
+    """One group at a time (max_groups = 1): requests of other shapes wait for
+    the running group to drain and leave; a request beyond a group's
+    capacities (M above N/4, K above N/64) gets a group of its own; K = 1
+    joins finish at once.  Every result equals solving alone."""
+    shapes = [("F", 1 << 15, 6000, 200, "cgauss", 7501), ("H", 1 << 16, 9000, 50, "gauss", 7502),
+              ("F", 1 << 15, 12000, 700, "cgauss", 7503),   # M > N/4, K > N/64
+              ("F", 1 << 15, 5000, 1, "cgauss", 7504), ("H", 1 << 16, 16000, 1100, "gauss", 7505),
+              ("F", 1 << 15, 7000, 90, "cgauss", 7506)]
+    data = _insts(shapes)
+    srv = fc.Server(4 << 30, max_groups=1, n_streams=2)
+    ts = [srv.submit(i.cls, i.N, i.M, i.K, i.omega, y, precision="fp32") for i, y in data]
+    srv.drain(300000)
+    got = [srv.poll(t) for t in ts]
+    info = srv.info()
+    srv.close()
+    assert info["completed"] == len(data) and info["slot_joins"] == len(data)
+    assert info["groups"] >= 3
+    for (i, y), g in zip(data, got):
+        sup, x = _alone(fc, i, y)
+        assert np.array_equal(g["support"], sup), (i.cls, i.N, i.M, i.K)
+        assert np.array_equal(g["x"], x)
+
+
+def test_slot_server_close_with_running_groups(fc):
+    """Closing the server while groups run: running requests finish, queued
+    ones are dropped, and nothing hangs."""
+    data = _insts(SHAPES[:4])
+    srv = fc.Server(4 << 30)
+    for i, y in data:
+        srv.submit(i.cls, i.N, i.M, i.K, i.omega, y, precision="fp32")
+    time.sleep(0.01)
+    t0 = time.time()
+    srv.close()
+    assert time.time() - t0 < 120

@@ -276,20 +276,29 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
 
 // ---------------------------------------------------------------------------
 // The same update split over G workgroups per instance for long supports:
-//   ls_a: identification, Gram column, w = W g (rows cyclic over G*4 waves)
-//   ls_b: partial sums of w^H W over the rows i = gid (mod G)
-//   ls_c: d (and the breakdown test), v = -(sum over the G partials, in
-//         order)/d, new row of W, z and x
-// Every reduction has a fixed order, so results depend on t only.
-template <bool FOURIER>
-__global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
+//   ls_ab: identification, Gram column, then for the rows i = gid (mod G),
+//          eight at a time: w_i = (W g)_i (two rows per wave) and, while
+//          those rows are still in the cache, the partial row
+//          sum_i conj(w_i) W(i, k) (thread per column k)
+//   ls_c:  d (and the breakdown test), v = -(sum over the G partials, in
+//          order)/d, new row of W, z and x
+// W is read from memory once per iteration.  Every reduction has a fixed
+// order (rows of a partial in increasing order, partials in gid order), so
+// results depend on t only.
+constexpr int L_RW = 2;                       // rows per wave in a batch
+constexpr int L_BATCH = L_RW * (L_THREADS / 64);   // rows per batch
+
+template <bool FOURIER, int KPT>
+__global__ void __launch_bounds__(L_THREADS) ls_ab_kernel(LParams p) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Sel red[16];
-  const int inst = blockIdx.y, gid = blockIdx.x, G = gridDim.x;
+  __shared__ Wd wl[L_BATCH];
+  const int inst = blockIdx.y, gid = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
-  if (p.tofs && ls_split_groups(t) == 1) return;   // the one-workgroup update takes it
+  const int G = ls_split_groups(t);
+  if (G == 1 || gid >= G) return;   // the one-workgroup update takes it / spare workgroup
   const int n = t - 1;
   Status* st = p.status + inst;
   // loads whose addresses do not depend on the outcome go out together: the
@@ -333,9 +342,97 @@ __global__ void __launch_bounds__(L_THREADS) ls_a_kernel(LParams p) {
   for (int i = tid + L_THREADS; i < n; i += L_THREADS)
     g[i] = c64[perm_index(FOURIER, (uint32_t)lam[i], j, mask)];
   __syncthreads();
-  const int nw = G * (L_THREADS / 64);
-  for (int i0 = (gid * (L_THREADS / 64) + wave) * L_RB; i0 < n; i0 += nw * L_RB)
-    ls_rows_wg<FOURIER>(W, g, i0, n, lane, wout);
+
+  Wd acc[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) acc[q] = vzero(Wd());
+  const int nq = (n + L_THREADS - 1) / L_THREADS;
+  for (int b0 = gid; b0 < n; b0 += L_BATCH * G) {
+    // ---- w for the wave's rows r_u = b0 + G (L_RW wave + u): lane-strided
+    // partial sums over k in increasing order, then a butterfly sum
+    int rr[L_RW];
+    int rmax = -1;
+#pragma unroll
+    for (int u = 0; u < L_RW; ++u) {
+      rr[u] = b0 + G * (L_RW * wave + u);
+      if (rr[u] < n) rmax = rr[u];
+    }
+    Wd sw[L_RW];
+#pragma unroll
+    for (int u = 0; u < L_RW; ++u) sw[u] = vzero(Wd());
+    for (int k0 = lane; k0 <= rmax; k0 += 64 * L_KU) {
+      Wd a[L_KU][L_RW], gk[L_KU];
+#pragma unroll
+      for (int v = 0; v < L_KU; ++v) {
+        const int kc = min(k0 + 64 * v, rmax);
+        gk[v] = g[kc];
+#pragma unroll
+        for (int u = 0; u < L_RW; ++u) {
+          const int r = min(rr[u], rmax);
+          a[v][u] = W[(int64_t)r * (r + 1) / 2 + min(kc, r)];
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < L_KU; ++v) {
+        const int k = k0 + 64 * v;
+#pragma unroll
+        for (int u = 0; u < L_RW; ++u) {
+          if (rr[u] < n && k <= rr[u]) {
+            if constexpr (FOURIER) {
+              const double2 tt = cmul(a[v][u], gk[v]);
+              sw[u].x += tt.x;
+              sw[u].y += tt.y;
+            } else {
+              sw[u] += a[v][u] * gk[v];
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < L_RW; ++u) {
+      if constexpr (FOURIER) { sw[u].x = wave_sum(sw[u].x); sw[u].y = wave_sum(sw[u].y); }
+      else sw[u] = wave_sum(sw[u]);
+      if (lane == 0) {
+        wl[L_RW * wave + u] = sw[u];
+        if (rr[u] < n) wout[rr[u]] = sw[u];
+      }
+    }
+    __syncthreads();
+    // ---- the batch's rows, in increasing order, into the partial row
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int k = tid + q * L_THREADS;
+      if (q < nq && k < n) {
+        Wd a[L_BATCH];
+#pragma unroll
+        for (int m = 0; m < L_BATCH; ++m) {
+          const int r = b0 + G * m;
+          a[m] = (r < n && k <= r) ? W[(int64_t)r * (r + 1) / 2 + k] : vzero(Wd());
+        }
+#pragma unroll
+        for (int m = 0; m < L_BATCH; ++m) {
+          const int r = b0 + G * m;
+          if (r < n && k <= r) {
+            if constexpr (FOURIER) {
+              const double2 tt = cmulc(wl[m], a[m]);
+              acc[q].x += tt.x;
+              acc[q].y += tt.y;
+            } else {
+              acc[q] += wl[m] * a[m];
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();   // wl is rewritten by the next batch
+  }
+  Wd* vp = (Wd*)p.vpart + (int64_t)inst * p.inst_vpart + (int64_t)gid * p.vpart_stride;
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + q * L_THREADS;
+    if (q < nq && k < n) vp[k] = acc[q];
+  }
 }
 
 template <bool FOURIER>
@@ -363,34 +460,6 @@ __device__ __forceinline__ bool ls_d(const LParams& p, int inst, int n, double* 
   if (!(d2 > 1e-13 * gamma)) return false;
   invd = 1.0 / sqrt(d2);
   return true;
-}
-
-template <bool FOURIER, int KPT>
-__global__ void __launch_bounds__(L_THREADS) ls_b_kernel(LParams p) {
-  using Wd = typename std::conditional<FOURIER, double2, double>::type;
-  const int inst = blockIdx.y, gid = blockIdx.x;
-  Status* st = p.status + inst;
-  if (st->done) return;
-  const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
-  // the row split is that of the instance's own iteration
-  const int G = p.tofs ? ls_split_groups(t) : (int)gridDim.x;
-  if (G == 1 || gid >= G) return;
-  const int tid = threadIdx.x;
-  const int n = t - 1;
-  // the partial sums do not need d: the breakdown test is left to ls_c
-  const Wd* w = (const Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
-  const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
-  Wd acc[KPT];
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) acc[q] = vzero(Wd());
-  const int nq = (n + L_THREADS - 1) / L_THREADS;
-  ls_rows_wh<FOURIER, KPT, L_VB>(W, w, gid, G, n, nq, tid, acc);
-  Wd* vp = (Wd*)p.vpart + (int64_t)inst * p.inst_vpart + (int64_t)gid * p.vpart_stride;
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * L_THREADS;
-    if (q < nq && k < n) vp[k] = acc[q];
-  }
 }
 
 template <bool FOURIER>
@@ -481,7 +550,9 @@ template <bool FOURIER, int KPT>
 static hipError_t launch_ls_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
                                 hipStream_t st) {
   if (split) {
-    hipLaunchKernelGGL((ls_b_kernel<FOURIER, KPT>), dim3(G, ninst), dim3(L_THREADS), 0, st, p);
+    hipError_t e = raise_lds_limit((const void*)ls_ab_kernel<FOURIER, KPT>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ls_ab_kernel<FOURIER, KPT>), dim3(G, ninst), dim3(L_THREADS), lds, st, p);
   } else {
     hipError_t e = raise_lds_limit((const void*)ls_kernel<FOURIER, KPT>, lds);
     if (e != hipSuccess) return e;
@@ -504,18 +575,10 @@ static hipError_t launch_ls_by_kpt(const LParams& p, int ninst, int G, bool spli
 
 template <bool FOURIER>
 static hipError_t launch_ls_split(const LParams& p, int ninst, int G, int n, hipStream_t st) {
-  const size_t lds_a = (size_t)n * (FOURIER ? 16 : 8) + 16;
+  const size_t lds = (size_t)n * (FOURIER ? 16 : 8) + 16;   // the Gram column
   const int cblocks = (n + L_THREADS - 1) / L_THREADS;
-  // w = W g: with few instances, enough workgroups that every wave takes one
-  // group of L_RB rows, up to about 1024 in all (the row-to-wave assignment
-  // does not change any sum)
-  const int waves = L_THREADS / 64;
-  const int Ga = std::max(G, std::min((n + L_RB * waves - 1) / (L_RB * waves),
-                                      (1024 + ninst - 1) / ninst));
-  hipError_t e = raise_lds_limit((const void*)ls_a_kernel<FOURIER>, lds_a);
+  hipError_t e = launch_ls_by_kpt<FOURIER>(p, ninst, G, true, lds, n, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ls_a_kernel<FOURIER>, dim3(Ga, ninst), dim3(L_THREADS), lds_a, st, p);
-  if ((e = launch_ls_by_kpt<FOURIER>(p, ninst, G, true, 0, n, st)) != hipSuccess) return e;
   hipLaunchKernelGGL(ls_c_kernel<FOURIER>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
   return hipGetLastError();
 }

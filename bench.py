@@ -402,6 +402,8 @@ def cfg2_leg(fc, device):
                    "ms_select": round(s.ms_select, 2), "iterations": int(s.iterations),
                    "support_set_equal": sorted(sup.tolist()) == sorted(ref["support"]),
                    "x_rel_err": float(np.linalg.norm(xv[o1] - xr[o2]) / np.linalg.norm(xr))}
+            if alg == "omp" and meth == "conventional":
+                sup_omp = sup.tolist()
             if alg == "omp":
                 g = np.array(gold["omp"]["gaps"])
                 first = int(np.argmax(g < 2.5e-5))
@@ -415,6 +417,25 @@ def cfg2_leg(fc, device):
                     rec["corr_us_per_iteration"] = round(per * 1e3, 2)
                     rec["corr_GBps_algorithmic"] = round(byts / (per / 1e3) / 1e9, 1)
             out[f"{alg}_{meth}"] = rec
+    # the same OMP solve replayed from one captured graph (a one-problem batch
+    # plan): the per-iteration launches without host launch overhead
+    import torch
+    bp = fc.BatchPlan([("H", NN, MM, KK, inst.omega)], method="conventional", precision="fp32",
+                      device=device)
+    bp.solve([y])
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bp.solve([y])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    gsup = bp.support[0].cpu().numpy()
+    out["omp_conventional_graph"] = {
+        "ms_per_solve": round(wall * 1e3, 2),
+        "support_equal_eager": gsup.tolist() == sup_omp,
+        "note": "one-problem batch plan: the solve's launches replayed from one captured graph"}
+    bp.close()
     return out
 
 

@@ -243,3 +243,23 @@ def test_schedule_host_only(fc, tmp_path):
     p.write_text("sched gfx-none 1 65536 1 4 1024 128 0\n1 8388608 1 7\nbogus line\n")
     fc.autotune_load(str(p))
     assert not fc.schedule_get("F", 1 << 16, "fp32", 256)["tuned"]
+
+
+def test_slot_group_footprint_capacities(fc):
+    """OMP with the fused conventional correlation is admitted as a one-slot
+    group at capacities (M up to N/4, N/2 or N; K up to max(256, N/64) or the
+    next power of two), so the footprint is flat inside a capacity and steps
+    at its edges; other requests keep their wave footprint, growing with K."""
+    N = 1 << 16
+    om = np.arange(16384) * 4
+    f = {K: fc.server_footprint("F", N, 16384, K, om, precision="fp32") for K in (100, 1000, 1024,
+                                                                                    1025, 2000)}
+    assert f[100] == f[1000] == f[1024] < f[1025] == f[2000]
+    # the packed FP64 complex inverse factor of one slot at K capacity 2048
+    assert f[2000] - f[1024] >= (2048 * 2049 - 1024 * 1025) // 2 * 16
+    om2 = np.arange(20000) * 3   # M above N/4: the N/2 capacity
+    assert fc.server_footprint("F", N, 20000, 100, om2, precision="fp32") > f[100]
+    # adaptive requests run in waves: the footprint follows K itself
+    a1 = fc.server_footprint("F", N, 16384, 100, om, method="adaptive", precision="fp32")
+    a2 = fc.server_footprint("F", N, 16384, 1000, om, method="adaptive", precision="fp32")
+    assert a1 < a2 < f[1000]

@@ -187,6 +187,16 @@ def batch_leg(fc, device, count: int, steps: int, plain_n: int):
         par += int(list(sup[k].cpu().numpy()) == e["support"])
         xerr = max(xerr, float(np.linalg.norm(xb[k].cpu().numpy() - xr) / np.linalg.norm(xr)))
     bp.close()
+    # the same batch with the paper's fast correlation and the adaptive method
+    # (persistent kernel: the kernel vector gathered from LDS)
+    other = {}
+    for meth in ("fast", "adaptive"):
+        bpm = fc.BatchPlan(probs, method=meth, precision="fp32", device=device)
+        bpm.solve(ys)
+        torch.cuda.synchronize()
+        tm = time_steps(lambda: bpm.solve(ys), steps, 0)
+        other[meth] = {"solves_per_s": round(count / tm, 1), "ms_per_batch": round(tm * 1e3, 3)}
+        bpm.close()
     lat = []
     idx = np.linspace(0, count - 1, plain_n).astype(int)
     for k in idx:
@@ -204,6 +214,7 @@ def batch_leg(fc, device, count: int, steps: int, plain_n: int):
                           "p99": round(float(np.percentile(done_ms, 99)), 3),
                           "max": round(float(done_ms.max()), 3)},
         "plan_create_ms": round(t_create * 1e3, 1),
+        "methods": other,
         "support_recovery_rate": rec,
         "oracle_parity": {"instances": 6 if count == 4096 else 0, "support_equal": par,
                           "x_rel_err_max": xerr,

@@ -150,6 +150,11 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
   int iters = 0;
   bool numeric = false;
   V* tile = (V*)s.tile;
+  // fast iterations gather the kernel vector from LDS: the transform tile
+  // (at least N values) holds it until the first conventional iteration;
+  // the least-squares update borrows the tile's first 2(t - 1) wide values
+  // for g and w, so later fast iterations restore only that prefix
+  bool c_in_tile = false;
   for (int t = 1; t <= K; ++t) {
     double bk = -1.0, bk2 = -1.0;
     int64_t bi = -1;
@@ -158,6 +163,12 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
     if (t == 1) {
       for (int j = tid; j < N; j += WG_THREADS) sel_add(vmag2(h0[j]), (int64_t)j, bk, bi, bk2);
     } else if (fast) {
+      const int cl = c_in_tile
+                         ? min(N, (int)((2 * (size_t)t * sizeof(Wd) + sizeof(V) - 1) / sizeof(V)))
+                         : N;
+      for (int jj = tid; jj < cl; jj += WG_THREADS) tile[jj] = cp[jj];
+      __syncthreads();
+      c_in_tile = true;
       // eq. (kernelsumOMP): h = h_0 - sum_tau x_tau P_{lam_tau} c, FP64 accumulation
       for (int j0 = tid; j0 < N; j0 += WG_THREADS * 4) {
         Wd acc[4];
@@ -172,7 +183,7 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const uint32_t j = (uint32_t)(j0 + u * WG_THREADS) & mask;
-            const Wd cw = vwiden(cp[perm_index(F, j, l, mask)]);
+            const Wd cw = vwiden(tile[perm_index(F, j, l, mask)]);
             if constexpr (F) {
               acc[u].x -= xv.x * cw.x - xv.y * cw.y;
               acc[u].y -= xv.x * cw.y + xv.y * cw.x;
@@ -190,6 +201,7 @@ __device__ void wg_solve(const WgParams& p, const WgDesc& d, const WgLds& s, Sta
       }
     } else {
       // conventional: FP64 residual r = y - Phi_t x_t, zero-filled into the tile
+      c_in_tile = false;
       for (int e = tid; e < N + (N >> 5) + 1; e += WG_THREADS) tile[e] = vzero(V());
       __syncthreads();
       for (int m0 = tid; m0 < M; m0 += WG_THREADS * 4) {

@@ -151,3 +151,42 @@ def test_slot_server_close_with_running_groups(fc):
     t0 = time.time()
     srv.close()
     assert time.time() - t0 < 120
+
+
+def test_slot_groups_beside_waves(fc):
+    """Slot-group requests (conventional OMP) served together with wave
+    requests (adaptive and fast OMP, SP, CoSaMP, and small problems on the
+    persistent kernel): every result equals the same request solved alone."""
+    import torch
+    reqs = []
+    for k, (cls, N, M, K, law, seed) in enumerate(SHAPES[:5]):
+        reqs.append((cls, N, M, K, law, seed, "omp", "conventional"))
+    reqs += [("F", 1 << 15, 6000, 120, "cgauss", 7601, "omp", "adaptive"),
+             ("H", 1 << 16, 9000, 80, "gauss", 7602, "omp", "fast"),
+             ("F", 1 << 15, 4000, 40, "cgauss", 7603, "sp", "conventional"),
+             ("H", 1 << 16, 6000, 30, "gauss", 7604, "cosamp", "fast"),
+             ("F", 4096, 1000, 30, "cgauss", 7605, "omp", "conventional")]
+    data = []
+    for cls, N, M, K, law, seed, alg, meth in reqs:
+        i = instancegen.draw_instance(cls, N, M, K, law, 30.0, seed)
+        data.append((i, oracle.problem.instance_measure(i, tier="transform"), alg, meth))
+    srv = fc.Server(8 << 30)
+    ts = [srv.submit(i.cls, i.N, i.M, i.K, i.omega, y, algorithm=alg, method=meth, precision="fp32")
+          for i, y, alg, meth in data]
+    srv.drain(300000)
+    got = [srv.poll(t) for t in ts]
+    info = srv.info()
+    srv.close()
+    assert info["completed"] == len(data)
+    assert info["slot_joins"] == 5 and info["waves"] >= 2
+    for (i, y, alg, meth), g in zip(data, got):
+        yd = torch.from_numpy(np.asarray(y)).to("cuda")
+        r = fc.solve(i.cls, i.N, i.M, i.K, i.omega, yd, algorithm=alg, method=meth, precision="fp32")
+        sup, x = r.support.cpu().numpy(), r.x.cpu().numpy()
+        if alg == "omp":
+            assert np.array_equal(g["support"], sup), (alg, meth, i.N)
+            assert np.array_equal(g["x"], x), (alg, meth, i.N)
+        else:   # set pursuits: the support as a set, x aligned with it
+            assert np.array_equal(np.sort(g["support"]), np.sort(sup)), (alg, meth, i.N)
+            assert np.allclose(g["x"][np.argsort(g["support"])], x[np.argsort(sup)], rtol=0,
+                               atol=1e-12 * np.abs(x).max())

@@ -285,12 +285,15 @@ __global__ void __launch_bounds__(L_THREADS) ls_kernel(LParams p) {
 // W is read from memory once per iteration.  Every reduction has a fixed
 // order (rows of a partial in increasing order, partials in gid order), so
 // results depend on t only.
-constexpr int L_RW = 2;                       // rows per wave in a batch
-constexpr int L_BATCH = L_RW * (L_THREADS / 64);   // rows per batch
+constexpr int L_RW = 2;      // rows per wave in a batch
+constexpr int L_AB = 8;      // rows per step of the partial-row fold (loads in flight)
 
-template <bool FOURIER, int KPT>
-__global__ void __launch_bounds__(L_THREADS) ls_ab_kernel(LParams p) {
+// NT threads per workgroup (256, or 1024 for launches of few workgroups):
+// neither the row-to-wave assignment nor the thread count changes a sum.
+template <bool FOURIER, int KPT, int NT>
+__global__ void __launch_bounds__(NT) ls_ab_kernel(LParams p) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
+  constexpr int L_BATCH = L_RW * (NT / 64);   // rows per batch
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Sel red[16];
   __shared__ Wd wl[L_BATCH];
@@ -319,7 +322,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_ab_kernel(LParams p) {
   double bk = -1.0, bk2 = -1.0;
   int64_t bi = -1;
   if (s0.idx >= 0) { bk = s0.key; bi = s0.idx; bk2 = s0.key2; }
-  for (int e = tid + L_THREADS; e < p.npart; e += L_THREADS) {
+  for (int e = tid + NT; e < p.npart; e += NT) {
     const Sel s = part[e];
     if (s.idx >= 0) sel_merge(s.key, s.idx, s.key2, bk, bi, bk2);
   }
@@ -339,14 +342,14 @@ __global__ void __launch_bounds__(L_THREADS) ls_ab_kernel(LParams p) {
   const Wd* W = (const Wd*)p.W + (int64_t)inst * p.inst_W;
   Wd* wout = (Wd*)p.wbuf + (int64_t)inst * p.inst_wbuf;
   if (tid < n) g[tid] = c64[perm_index(FOURIER, (uint32_t)l0, j, mask)];
-  for (int i = tid + L_THREADS; i < n; i += L_THREADS)
+  for (int i = tid + NT; i < n; i += NT)
     g[i] = c64[perm_index(FOURIER, (uint32_t)lam[i], j, mask)];
   __syncthreads();
 
   Wd acc[KPT];
 #pragma unroll
   for (int q = 0; q < KPT; ++q) acc[q] = vzero(Wd());
-  const int nq = (n + L_THREADS - 1) / L_THREADS;
+  const int nq = (n + NT - 1) / NT;
   for (int b0 = gid; b0 < n; b0 += L_BATCH * G) {
     // ---- w for the wave's rows r_u = b0 + G (L_RW wave + u): lane-strided
     // partial sums over k in increasing order, then a butterfly sum
@@ -402,24 +405,26 @@ __global__ void __launch_bounds__(L_THREADS) ls_ab_kernel(LParams p) {
     // ---- the batch's rows, in increasing order, into the partial row
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
-      const int k = tid + q * L_THREADS;
+      const int k = tid + q * NT;
       if (q < nq && k < n) {
-        Wd a[L_BATCH];
+        for (int m0 = 0; m0 < L_BATCH && b0 + G * m0 < n; m0 += L_AB) {
+          Wd a[L_AB];
 #pragma unroll
-        for (int m = 0; m < L_BATCH; ++m) {
-          const int r = b0 + G * m;
-          a[m] = (r < n && k <= r) ? W[(int64_t)r * (r + 1) / 2 + k] : vzero(Wd());
-        }
+          for (int u = 0; u < L_AB; ++u) {
+            const int r = b0 + G * (m0 + u);
+            a[u] = (r < n && k <= r) ? W[(int64_t)r * (r + 1) / 2 + k] : vzero(Wd());
+          }
 #pragma unroll
-        for (int m = 0; m < L_BATCH; ++m) {
-          const int r = b0 + G * m;
-          if (r < n && k <= r) {
-            if constexpr (FOURIER) {
-              const double2 tt = cmulc(wl[m], a[m]);
-              acc[q].x += tt.x;
-              acc[q].y += tt.y;
-            } else {
-              acc[q] += wl[m] * a[m];
+          for (int u = 0; u < L_AB; ++u) {
+            const int r = b0 + G * (m0 + u);
+            if (r < n && k <= r) {
+              if constexpr (FOURIER) {
+                const double2 tt = cmulc(wl[m0 + u], a[u]);
+                acc[q].x += tt.x;
+                acc[q].y += tt.y;
+              } else {
+                acc[q] += wl[m0 + u] * a[u];
+              }
             }
           }
         }
@@ -430,7 +435,7 @@ __global__ void __launch_bounds__(L_THREADS) ls_ab_kernel(LParams p) {
   Wd* vp = (Wd*)p.vpart + (int64_t)inst * p.inst_vpart + (int64_t)gid * p.vpart_stride;
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * L_THREADS;
+    const int k = tid + q * NT;
     if (q < nq && k < n) vp[k] = acc[q];
   }
 }
@@ -550,9 +555,20 @@ template <bool FOURIER, int KPT>
 static hipError_t launch_ls_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
                                 hipStream_t st) {
   if (split) {
-    hipError_t e = raise_lds_limit((const void*)ls_ab_kernel<FOURIER, KPT>, lds);
+    // few workgroups in all: 1024 threads each (more rows and loads in
+    // flight), a quarter of the columns per thread
+    if ((int64_t)G * ninst < 512) {
+      constexpr int K4 = KPT >= 4 ? KPT / 4 : 1;
+      hipError_t e = raise_lds_limit((const void*)ls_ab_kernel<FOURIER, K4, 1024>, lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((ls_ab_kernel<FOURIER, K4, 1024>), dim3(G, ninst), dim3(1024), lds, st,
+                         p);
+      return hipGetLastError();
+    }
+    hipError_t e = raise_lds_limit((const void*)ls_ab_kernel<FOURIER, KPT, L_THREADS>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ls_ab_kernel<FOURIER, KPT>), dim3(G, ninst), dim3(L_THREADS), lds, st, p);
+    hipLaunchKernelGGL((ls_ab_kernel<FOURIER, KPT, L_THREADS>), dim3(G, ninst), dim3(L_THREADS),
+                       lds, st, p);
   } else {
     hipError_t e = raise_lds_limit((const void*)ls_kernel<FOURIER, KPT>, lds);
     if (e != hipSuccess) return e;

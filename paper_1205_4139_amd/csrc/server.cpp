@@ -678,18 +678,18 @@ void group_main(fcmp_server* S, SlotGroup* G) {
   char* res = (char*)stg.p;
   char* ring = res + (size_t)n * res_b;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  int64_t ev_round[3] = {-1, -1, -1};
+  int64_t ev_cycle[3] = {-1, -1, -1};
   for (int q = 0; q < 3 && !rc; ++q)
     if (hipEventCreateWithFlags(&ev[q], hipEventBlockingSync | hipEventDisableTiming) != hipSuccess)
       rc = set_error(FCMP_E_DEVICE, "event creation failed");
   struct Pend {
     int s;
     Req* r;
-    int64_t round;
+    int64_t cycle;
   };
   std::vector<Pend> pend;
   std::vector<int> tofs((size_t)n, 0), Ms((size_t)n, 0), Ks((size_t)n, 0), run((size_t)n, 0);
-  int64_t round = 0, done_round = -1;
+  int64_t cycle = 0, done_cycle = -1;
   int step = 2;
   bool tw_loaded = false;
   int64_t n_res = 0, n_copy = 0, n_steps = 0;
@@ -702,20 +702,20 @@ void group_main(fcmp_server* S, SlotGroup* G) {
     used += pad256(bytes);
     return d;
   };
-  auto wait_round = [&](int64_t r) -> int {
-    if (r <= done_round) return FCMP_OK;
+  auto wait_cycle = [&](int64_t r) -> int {
+    if (r <= done_cycle) return FCMP_OK;
     const int q = (int)(r % 3);
-    if (ev_round[q] != r) return set_error(FCMP_E_DEVICE, "slot group: round event lost");
+    if (ev_cycle[q] != r) return set_error(FCMP_E_DEVICE, "slot group: cycle event lost");
     HIP_TRY(hipEventSynchronize(ev[q]));
-    done_round = r;
+    done_cycle = r;
     return FCMP_OK;
   };
-  // results of finished slots whose round is complete back to their requests
+  // results of finished slots whose cycle is complete back to their requests
   auto deliver = [&](bool all) {
     std::vector<Pend> keep;
     std::vector<Req*> fin;
     for (const Pend& d : pend) {
-      if (!all && d.round > done_round) {
+      if (!all && d.cycle > done_cycle) {
         keep.push_back(d);
         continue;
       }
@@ -755,7 +755,7 @@ void group_main(fcmp_server* S, SlotGroup* G) {
       place_slot_requests(S);
     }
   };
-  // round 0: the slots' device pointers, every slot done, offsets zero
+  // cycle 0: the slots' device pointers, every slot done, offsets zero
   if (!rc) {
     seg = ring;
     used = 0;
@@ -772,11 +772,11 @@ void group_main(fcmp_server* S, SlotGroup* G) {
         launch_fill_u32((uint32_t*)tofs_dev, 0u, n, st) != hipSuccess ||
         hipEventRecord(ev[0], st) != hipSuccess)
       rc = set_error(FCMP_E_DEVICE, "slot group set-up failed");
-    ev_round[0] = 0;
-    round = 1;
+    ev_cycle[0] = 0;
+    cycle = 1;
   }
   while (!rc) {
-    if (round >= 2 && (rc = wait_round(round - 2))) break;
+    if (cycle >= 2 && (rc = wait_cycle(cycle - 2))) break;
     deliver(false);
     std::vector<int> js;
     {
@@ -803,12 +803,12 @@ void group_main(fcmp_server* S, SlotGroup* G) {
         continue;
       }
     }
-    seg = ring + (size_t)(round % 3) * seg_b;
+    seg = ring + (size_t)(cycle % 3) * seg_b;
     used = 0;
     std::vector<int> fin_now;   // slots done at their join (K = 1)
     size_t j = 0;
     for (; j < js.size() && !rc; ++j) {
-      if (j > 0 && used + join_b > seg_b) break;   // the rest join next round
+      if (j > 0 && used + join_b > seg_b) break;   // the rest join next cycle
       const int s = js[j];
       Req* r = G->occ[(size_t)s];
       const int32_t M = (int32_t)r->prob.M, K = (int32_t)r->prob.K;
@@ -879,7 +879,7 @@ void group_main(fcmp_server* S, SlotGroup* G) {
     // finished slots: results to their staging, the slot free for a new request
     for (int s : fin) {
       for (const Pend& d : pend)
-        if (d.s == s && (rc = wait_round(d.round))) break;
+        if (d.s == s && (rc = wait_cycle(d.cycle))) break;
       if (rc) break;
       deliver(false);
       fcmp_plan V = plan_view(P, s, Ms[(size_t)s], Ks[(size_t)s]);
@@ -896,20 +896,20 @@ void group_main(fcmp_server* S, SlotGroup* G) {
         break;
       }
       run[(size_t)s] = 0;
-      pend.push_back(Pend{s, r, round});
+      pend.push_back(Pend{s, r, cycle});
       std::lock_guard<std::mutex> lk(S->mu);
       G->occ[(size_t)s] = nullptr;
       G->joined[(size_t)s] = 0;
       place_slot_requests(S);
     }
     if (rc) break;
-    const int q = (int)(round % 3);
+    const int q = (int)(cycle % 3);
     if (hipEventRecord(ev[q], st) != hipSuccess) {
       rc = set_error(FCMP_E_DEVICE, "slot group: event record failed");
       break;
     }
-    ev_round[q] = round;
-    round++;
+    ev_cycle[q] = cycle;
+    cycle++;
   }
   // wind down: nothing of the group may still use its region
   if (rc) msg = last_error();

@@ -33,8 +33,11 @@ constexpr size_t rr_region_a(size_t vc_bytes) {
 }
 }  // namespace
 
+// Four workgroups per CU (four waves per SIMD) when the LDS footprint allows:
+// the kernel is latency-bound, so residency matters more than the few
+// registers the bound costs.
 template <bool FFT, class VC>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 rcorr_reg_kernel(RCParams p) {
   using VR = typename std::conditional<FFT, double2, double>::type;
   using SC = typename VT<VC>::S;
@@ -54,7 +57,8 @@ rcorr_reg_kernel(RCParams p) {
   if (p.Kv && ntaps >= p.Kv[inst]) return;   // its K selections are made
 
   // LDS: region A (staged taps; then the exchange buffers; then the output
-  // tile), then the inter-pass twiddles of the correlation precision
+  // tile), then W_N1^q in FP64 (the tap sums' factors, and, rounded to the
+  // correlation precision, the twiddles of the first-pass transform)
   constexpr size_t bytesA = rr_region_a(sizeof(VC));
   int32_t* tl = (int32_t*)smem_raw;
   VR* tx = (VR*)(smem_raw + RR_TAPS * 4);
@@ -62,15 +66,13 @@ rcorr_reg_kernel(RCParams p) {
   double* xr = (double*)smem_raw + wave * RR_XW + grp * (16 * 17);
   SC* xc = (SC*)((double*)smem_raw + wave * RR_XW) + grp * (16 * 17);
   VC* tile = (VC*)smem_raw;
-  VC* twlo = (VC*)(smem_raw + bytesA);
-  const int nlo = 1 << p.twS, nhi = p.N >> p.twS;
-  VC* twhi = twlo + nlo;
-  // Fourier: W_N1^q (FP64) for the tap sums, after the correlation twiddles
-  double2* t1 = (double2*)(((uintptr_t)(twhi + (FFT ? nhi : 0)) + 15) & ~(uintptr_t)15);
+  const int nhi = p.N >> p.twS;       // N1
+  double2* t1 = (double2*)(smem_raw + bytesA);
 
   // Global loads with no dependence on this workgroup's LDS are issued first,
-  // so their latencies overlap: the first chunk of taps, the tables, the
-  // column masks of the residual and the per-register twiddle factors.
+  // so their latencies overlap: the first chunk of taps and the tables.  The
+  // column masks and the per-register twiddle factors are loaded after the
+  // tap sums (fewer registers live during them).
   const int32_t* bs = p.bstart + (int64_t)inst * p.inst_bstart + (ntaps & 1) * p.bstart_half;
   const int32_t* od = p.ord + (int64_t)inst * p.inst_ord + (ntaps & 1) * p.ord_half;
   const int32_t* lm = p.lam + (int64_t)inst * p.inst_lam;
@@ -82,30 +84,8 @@ rcorr_reg_kernel(RCParams p) {
     tlv0 = lm[tau];
     txv0 = xs[tau];
   }
-  const uint32_t* cm = p.cmask + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
-  const int32_t* cb = p.cbase + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
-  uint32_t mwv[FFT ? 8 : 1];
-  int32_t bwv[FFT ? 8 : 1];
-#pragma unroll
-  for (int w = 0; w < (FFT ? 8 : 1); ++w) {
-    mwv[w] = cm[FFT ? w : (pl >> 1)];
-    bwv[w] = cb[FFT ? w : (pl >> 1)];
-  }
-  double2 wl0 = make_double2(1.0, 0.0), wl16 = make_double2(1.0, 0.0);
-  if constexpr (FFT) {
-    // W_N^{l c} for l = pl + 16 a is W_N^{pl c} (W_N^{16 c})^a
-    const double2* rlo = (const double2*)p.twr_lo;
-    const double2* rhi = (const double2*)p.twr_hi;
-    const uint32_t lomask = (1u << p.twS) - 1u;
-    const uint32_t q0 = ((uint32_t)pl * cg) & maskN, q1 = (16u * cg) & maskN;
-    wl0 = cmul(rhi[q0 >> p.twS], rlo[q0 & lomask]);
-    wl16 = cmul(rhi[q1 >> p.twS], rlo[q1 & lomask]);
-  }
   for (int b = tid; b <= RR_L; b += 256) bsl[b] = ntaps > 0 ? bs[b] : 0;
   if constexpr (FFT) {
-    const VC* glo = (const VC*)p.twc_lo;
-    const VC* ghi = (const VC*)p.twc_hi;
-    for (int e = tid; e < nlo + nhi; e += 256) twlo[e] = e < nlo ? glo[e] : ghi[e - nlo];
     const double2* g1 = (const double2*)p.twr_hi;   // W_N^{q N2} = W_N1^q
     for (int e = tid; e < nhi; e += 256) t1[e] = g1[e];
   }
@@ -170,8 +150,30 @@ rcorr_reg_kernel(RCParams p) {
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  const uint32_t* cm = p.cmask + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
+  const int32_t* cb = p.cbase + (int64_t)inst * p.inst_cmask + (int64_t)cg * 8;
+  uint32_t mwv[FFT ? 8 : 1];
+  int32_t bwv[FFT ? 8 : 1];
+#pragma unroll
+  for (int w = 0; w < (FFT ? 8 : 1); ++w) {
+    mwv[w] = cm[FFT ? w : (pl >> 1)];
+    bwv[w] = cb[FFT ? w : (pl >> 1)];
+  }
+  // W_N^{pl c} and W_N^{16 c} (FP64): the powers W_N^{(pl + 16 a) c} are
+  // both the factor of register a of the tap sums and the inter-pass
+  // twiddle of output j2 = pl + 16 a (loaded twice rather than held)
+  auto lane_twiddles = [&](double2& w0, double2& w16) {
+    const double2* rlo = (const double2*)p.twr_lo;
+    const double2* rhi = (const double2*)p.twr_hi;
+    const uint32_t lomask = (1u << p.twS) - 1u;
+    const uint32_t q0 = ((uint32_t)pl * cg) & maskN, q1 = (16u * cg) & maskN;
+    w0 = cmul(rhi[q0 >> p.twS], rlo[q0 & lomask]);
+    w16 = cmul(rhi[q1 >> p.twS], rlo[q1 & lomask]);
+  };
   if constexpr (FFT) {
     // the factor W_N^{l c}, powers by repeated multiplication (FP64)
+    double2 wl0, wl16;
+    lane_twiddles(wl0, wl16);
     double2 w = wl0;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
@@ -229,19 +231,24 @@ rcorr_reg_kernel(RCParams p) {
   // ---- the correlation's first pass over the rows, + sign.  Fourier: rows
   // m = pl + 16 r in, outputs j2 = pl + 16 r; Hadamard: rows m = r + 16 pl
   // in, outputs j2 = pl + 16 r
+  double2 wj = make_double2(1.0, 0.0), wj16 = wj;
   if constexpr (FFT) {
-    reg_fft256(rc, xc, pl, [&](int q) { return twhi[q << dsh]; });
+    lane_twiddles(wj, wj16);
+    // W_256^q rounded from FP64 (the same values as a table built in the
+    // correlation precision: every entry rounds once to the same float)
+    reg_fft256(rc, xc, pl, [&](int q) { return vnarrow(t1[q << dsh], VC()); });
   } else {
     reg_wht256(rc, xc, pl);
   }
   __syncthreads();   // every exchange is done: region A becomes the output tile
+  // wj: W_N^{c j2}, powers in FP64, rounded once per output
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int j2 = pl + 16 * r;
     VC v = rc[r];
     if constexpr (FFT) {
-      const uint32_t q = (cg * (uint32_t)j2) & maskN;
-      v = cmul(v, tw_lookup(twlo, twhi, q, p.twS, +1));
+      v = cmul(v, vnarrow(wj, VC()));
+      if (r < 15) wj = cmul(wj, wj16);
     }
     tile[j2 * 17 + col] = v;
   }
@@ -262,9 +269,8 @@ bool rcorr_reg_ok(int pk, bool fft, const RCParams& p) {
 
 static size_t rcorr_reg_lds(int pk, bool fft, const RCParams& p) {
   const size_t bytesA = rr_region_a(vbytes(pk));
-  const size_t ntw = fft ? ((size_t)1 << p.twS) + ((size_t)p.N >> p.twS) : 0;
-  const size_t t1b = fft ? ((size_t)p.N >> p.twS) * 16 + 16 : 0;
-  return bytesA + ntw * vbytes(pk) + t1b;
+  const size_t t1b = fft ? ((size_t)p.N >> p.twS) * 16 : 0;
+  return bytesA + t1b;
 }
 
 template <bool FFT, class VC>

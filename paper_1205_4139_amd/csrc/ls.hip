@@ -290,14 +290,33 @@ constexpr int L_AB = 8;      // rows per step of the partial-row fold (loads in 
 
 // NT threads per workgroup (256, or 1024 for launches of few workgroups):
 // neither the row-to-wave assignment nor the thread count changes a sum.
+//
+// Workgroups are dispatched to the eight XCDs round-robin by linear id.  With
+// gx > 0 (a batch that is a multiple of 8) the grid is one-dimensional, gx
+// workgroups per instance, read so that all the workgroups of instance i run
+// on XCD i mod 8: the lines of the kernel vector that each of them gathers
+// for the Gram column are then fetched into one L2, not into all eight; the
+// split kernel that follows reads the partial rows on that XCD too.
+__device__ __forceinline__ void xcd_split(int gx, int& inst, int& part) {
+  if (gx > 0) {
+    const int L = blockIdx.x, k = L >> 3;
+    inst = (L & 7) + 8 * (k / gx);
+    part = k % gx;
+  } else {
+    inst = blockIdx.y;
+    part = blockIdx.x;
+  }
+}
+
 template <bool FOURIER, int KPT, int NT>
-__global__ void __launch_bounds__(NT) ls_ab_kernel(LParams p) {
+__global__ void __launch_bounds__(NT) ls_ab_kernel(LParams p, int gx) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
   constexpr int L_BATCH = L_RW * (NT / 64);   // rows per batch
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ Sel red[16];
   __shared__ Wd wl[L_BATCH];
-  const int inst = blockIdx.y, gid = blockIdx.x;
+  int inst, gid;
+  xcd_split(gx, inst, gid);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
   const int G = ls_split_groups(t);
@@ -468,10 +487,11 @@ __device__ __forceinline__ bool ls_d(const LParams& p, int inst, int n, double* 
 }
 
 template <bool FOURIER>
-__global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int Gl) {
+__global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int Gl, int cx) {
   using Wd = typename std::conditional<FOURIER, double2, double>::type;
   __shared__ double dred[16];
-  const int inst = blockIdx.y, cb = blockIdx.x;
+  int inst, cb;
+  xcd_split(cx, inst, cb);
   Status* st = p.status + inst;
   if (st->done) return;
   const int t = p.tofs ? p.t - p.tofs[inst] : p.t;
@@ -543,6 +563,12 @@ __global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int Gl) {
   if (cb == 0 && p.ord) tap_order_insert(p, inst, n, j);
 }
 
+// The XCD-grouped one-dimensional grid (see xcd_split) for a batch that is a
+// multiple of 8.
+static bool ls_xcd_map(int ninst, int per_inst) {
+  return ninst >= 8 && ninst % 8 == 0 && (int64_t)per_inst * ninst < (int64_t(1) << 31);
+}
+
 // Columns per thread of the w^H W product, rounded up to a power of two.
 static int ls_kpt(int n) {
   const int nq = (n + L_THREADS - 1) / L_THREADS;
@@ -555,20 +581,22 @@ template <bool FOURIER, int KPT>
 static hipError_t launch_ls_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
                                 hipStream_t st) {
   if (split) {
+    const bool xm = ls_xcd_map(ninst, G);
+    const dim3 grid = xm ? dim3(G * ninst) : dim3(G, ninst);
+    const int gx = xm ? G : 0;
     // few workgroups in all: 1024 threads each (more rows and loads in
     // flight), a quarter of the columns per thread
     if ((int64_t)G * ninst < 512) {
       constexpr int K4 = KPT >= 4 ? KPT / 4 : 1;
       hipError_t e = raise_lds_limit((const void*)ls_ab_kernel<FOURIER, K4, 1024>, lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((ls_ab_kernel<FOURIER, K4, 1024>), dim3(G, ninst), dim3(1024), lds, st,
-                         p);
+      hipLaunchKernelGGL((ls_ab_kernel<FOURIER, K4, 1024>), grid, dim3(1024), lds, st, p, gx);
       return hipGetLastError();
     }
     hipError_t e = raise_lds_limit((const void*)ls_ab_kernel<FOURIER, KPT, L_THREADS>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ls_ab_kernel<FOURIER, KPT, L_THREADS>), dim3(G, ninst), dim3(L_THREADS),
-                       lds, st, p);
+    hipLaunchKernelGGL((ls_ab_kernel<FOURIER, KPT, L_THREADS>), grid, dim3(L_THREADS), lds, st,
+                       p, gx);
   } else {
     hipError_t e = raise_lds_limit((const void*)ls_kernel<FOURIER, KPT>, lds);
     if (e != hipSuccess) return e;
@@ -595,7 +623,9 @@ static hipError_t launch_ls_split(const LParams& p, int ninst, int G, int n, hip
   const int cblocks = (n + L_THREADS - 1) / L_THREADS;
   hipError_t e = launch_ls_by_kpt<FOURIER>(p, ninst, G, true, lds, n, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ls_c_kernel<FOURIER>, dim3(cblocks, ninst), dim3(L_THREADS), 0, st, p, G);
+  const bool xm = ls_xcd_map(ninst, cblocks);
+  hipLaunchKernelGGL(ls_c_kernel<FOURIER>, xm ? dim3(cblocks * ninst) : dim3(cblocks, ninst),
+                     dim3(L_THREADS), 0, st, p, G, xm ? cblocks : 0);
   return hipGetLastError();
 }
 

@@ -330,3 +330,34 @@ def test_fused_residual_choice_independent_of_plan_size(fc):
         alone = fc.solve("F", N, M, K, inst.omega, to_dev(y), precision="fp64")
         assert np.array_equal(to_np(alone.support), sup[b])
         assert np.array_equal(to_np(alone.x), x[b])
+
+
+@pytest.mark.parametrize("cls", ["F", "H"])
+def test_split_update_batch_of_eight_matches_alone(fc, cls):
+    """A lockstep batch whose size is a multiple of 8 runs the split
+    least-squares update (t > 64) on the XCD-grouped grid; every instance
+    still equals its solve alone bit for bit (same rows per workgroup, same
+    sum order), and the oracle on certified instances."""
+    import torch
+    N, M, K = 8192, 2048, 100
+    law = "cgauss" if cls == "F" else "gauss"
+    data = _insts(cls, N, M, K, law, 30.0, 16, 8700)
+    plan = fc.Plan(cls, N, M, K, [d[0].omega for d in data], precision="fp32")
+    ys = torch.stack([to_dev(d[1]) for d in data])
+    sup, x, stats = plan.solve(ys, stats=True)
+    sup, x = to_np(sup).copy(), to_np(x).copy()
+    plan.close()
+    for b, (inst, y) in enumerate(data):
+        alone = fc.solve(cls, N, M, K, inst.omega, to_dev(y), precision="fp32")
+        assert np.array_equal(to_np(alone.support), sup[b]), b
+        assert np.array_equal(to_np(alone.x), x[b]), b
+        assert stats[b].iterations == K
+    checked = 0
+    for b in (0, 9):
+        inst, y = data[b]
+        ref = oracle.omp(oracle.make_operator(cls, N, inst.omega), y, K)
+        if certify.certified(ref, "fp32"):
+            assert list(sup[b]) == list(ref.support)
+            assert np.linalg.norm(x[b] - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+            checked += 1
+    assert checked >= 1

@@ -612,7 +612,11 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
 def summarize_sq(csv_path: str) -> dict:
     """Per-kernel SQ counter ratios from one rocprofv3 --pmc run of this script
     (the workload's grid, i.e. the most frequent grid of each kernel): each
-    counter divided by SQ_WAVE_CYCLES, the medians over that grid's dispatches."""
+    counter divided by SQ_WAVE_CYCLES, the medians over that grid's dispatches.
+    Instruction counters (SQ_INSTS_*) are also given per dispatch, and
+    SQ_INSTS_VALU as the time the vector ALUs need to issue them: a wave64
+    instruction occupies a 16-lane SIMD for 4 cycles, over 256 CUs x 4 SIMDs
+    at 2.4 GHz."""
     import csv
     import statistics
     from collections import Counter, defaultdict
@@ -631,6 +635,7 @@ def summarize_sq(csv_path: str) -> dict:
         if grids[g] < 10:
             continue
         ratios = defaultdict(list)
+        counts = defaultdict(list)
         for d in vals[g].values():
             wc = d.get("SQ_WAVE_CYCLES", 0.0)
             if wc <= 0:
@@ -638,8 +643,15 @@ def summarize_sq(csv_path: str) -> dict:
             for c, v in d.items():
                 if c != "SQ_WAVE_CYCLES":
                     ratios[c].append(v / wc)
+                if c.startswith("SQ_INSTS_"):
+                    counts[c].append(v)
         out[name] = {"grid": g[1], "dispatches": grids[g],
                      **{c: round(statistics.median(v), 4) for c, v in sorted(ratios.items())}}
+        if counts:
+            per = {c: statistics.median(v) for c, v in sorted(counts.items())}
+            out[name]["per_dispatch"] = {c: round(v) for c, v in per.items()}
+            if "SQ_INSTS_VALU" in per:
+                out[name]["valu_issue_us"] = round(per["SQ_INSTS_VALU"] * 4 / (256 * 4) / 2.4e3, 2)
     return out
 
 
@@ -817,11 +829,13 @@ def main():
         fc.solve("F", N, M, K, insts[i].omega, ys[i], precision="fp32", stats=True)
         lat.append(time.perf_counter() - t0)
     lat = np.array(lat[1:] if len(lat) > 1 else lat) * 1e3
-    plain = {"solves_per_s": round(1e3 / float(np.mean(lat)), 3),
-             "p50_ms": round(float(np.percentile(lat, 50)), 3),
-             "p99_ms": round(float(np.percentile(lat, 99)), 3),
-             "note": "fcmp_solve: one instance per call, kernel vector included, host-synchronised"}
-    print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
+    plain = None
+    if len(lat):
+        plain = {"solves_per_s": round(1e3 / float(np.mean(lat)), 3),
+                 "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                 "note": "fcmp_solve: one instance per call, kernel vector included, host-synchronised"}
+        print(f"[bench] plain: {plain}", file=sys.stderr, flush=True)
 
     batch = serve = None
     if args.batch_count > 0:

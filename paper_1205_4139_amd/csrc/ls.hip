@@ -563,10 +563,13 @@ __global__ void __launch_bounds__(L_THREADS) ls_c_kernel(LParams p, int Gl, int 
   if (cb == 0 && p.ord) tap_order_insert(p, inst, n, j);
 }
 
-// The XCD-grouped one-dimensional grid (see xcd_split) for a batch that is a
-// multiple of 8.
-static bool ls_xcd_map(int ninst, int per_inst) {
-  return ninst >= 8 && ninst % 8 == 0 && (int64_t)per_inst * ninst < (int64_t(1) << 31);
+// The XCD-grouped one-dimensional grid (see xcd_split) for a lockstep batch
+// that is a multiple of 8.  Not for slot groups: their slots sit at different
+// iterations or are free, and pinning each slot's workgroups to one XCD would
+// leave the XCDs of short or free slots idle.
+static bool ls_xcd_map(const LParams& p, int ninst, int per_inst) {
+  return !p.tofs && ninst >= 8 && ninst % 8 == 0 &&
+         (int64_t)per_inst * ninst < (int64_t(1) << 31);
 }
 
 // Columns per thread of the w^H W product, rounded up to a power of two.
@@ -581,7 +584,7 @@ template <bool FOURIER, int KPT>
 static hipError_t launch_ls_kpt(const LParams& p, int ninst, int G, bool split, size_t lds,
                                 hipStream_t st) {
   if (split) {
-    const bool xm = ls_xcd_map(ninst, G);
+    const bool xm = ls_xcd_map(p, ninst, G);
     const dim3 grid = xm ? dim3(G * ninst) : dim3(G, ninst);
     const int gx = xm ? G : 0;
     // few workgroups in all: 1024 threads each (more rows and loads in
@@ -623,7 +626,7 @@ static hipError_t launch_ls_split(const LParams& p, int ninst, int G, int n, hip
   const int cblocks = (n + L_THREADS - 1) / L_THREADS;
   hipError_t e = launch_ls_by_kpt<FOURIER>(p, ninst, G, true, lds, n, st);
   if (e != hipSuccess) return e;
-  const bool xm = ls_xcd_map(ninst, cblocks);
+  const bool xm = ls_xcd_map(p, ninst, cblocks);
   hipLaunchKernelGGL(ls_c_kernel<FOURIER>, xm ? dim3(cblocks * ninst) : dim3(cblocks, ninst),
                      dim3(L_THREADS), 0, st, p, G, xm ? cblocks : 0);
   return hipGetLastError();

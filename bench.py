@@ -698,8 +698,8 @@ def main():
         print(json.dumps(summarize_sq(args.summarize_sq), indent=1))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(instances would shard across GPUs with no exchange; see DESIGN.md)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(instances would shard across GPUs with no exchange between them)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -678,7 +678,7 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096, help="uneven batch leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=1000, help="serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=20000.0)
-    ap.add_argument("--serve-sweep", type=str, default="200,300,400,500,600,800",
+    ap.add_argument("--serve-sweep", type=str, default="200,300,350,400,450,500,600,800",
                     help="offered rates (req/s) of the serving sweep, '' to skip")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="seconds of arrivals per sweep rate")

@@ -51,10 +51,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kind: str):
-    """HBM bytes per launch from committed rocprofv3 PMC runs, if they were
-    taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+def traffic_for(kind: str, path: str | None = None):
+    """HBM bytes per launch from committed rocprofv3 PMC runs (path: default
+    profiles/pmc_traffic.json), if they were taken on the current kernel
+    sources (else None)."""
+    path = path or os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     try:
@@ -550,12 +551,13 @@ def serve_sweep(fc, device, rates, seconds: float):
             "criterion": "completed within the arrival window >= 95% of offered"}
 
 
-def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
+def summarize_pmc(fetch_csv: str, write_csv: str, out_path: str | None = None) -> dict:
     """HBM bytes per conventional-correlation launch pair (the residual fused
     with the complex64 first pass, then pass 2, at the workload's grid) from two rocprofv3 --pmc runs of this
     script (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by
     what the same counter reads for the plain copy of --copy-probe-mib MiB.
-    Written to profiles/pmc_traffic.json with the kernel-source hash."""
+    Written with the kernel-source hash to out_path (default
+    profiles/pmc_traffic.json)."""
     import csv
     import statistics
     from collections import Counter, defaultdict
@@ -602,7 +604,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> dict:
         "pass2_read": round(per[("FETCH_SIZE", "pass2")]),
         "pass2_write": round(per[("WRITE_SIZE", "pass2")]),
     }
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    path = out_path or os.path.join(ROOT, "profiles", "pmc_traffic.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
